@@ -1,0 +1,172 @@
+"""Moving-grid split-operator propagation on MI355X (gfx950).
+
+Time-reversible adaptive-grid integrator of Choi & Vanicek (arXiv:1909.06412):
+split-operator steps of the dynamic Fourier method on a tensor-product grid whose
+centres follow the Ehrenfest moments <p> and <dV/dq> within each kinetic and
+potential substep, composed symmetrically to orders 2-10.
+
+All arithmetic runs in libmgso.so (hand-written HIP kernels); this package only
+marshals arguments.  PyTorch, when present, provides device memory and the stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import (MgError, MG_C128, MG_C64, MG_POT_FREE, MG_POT_HARMONIC,  # noqa: F401
+                   MG_POT_MORSE_REP, MG_POT_HENON_HEILES, MG_POT_QUADRATIC, MG_TVT, MG_VTV,
+                   MG_COMP_STRANG, MG_COMP_SUZUKI, MG_COMP_TRIPLE_JUMP, MG_COMP_USER,
+                   MG_OPT_ENGINE, MG_OPT_GRAPH, MG_OPT_PROFILE, MG_OPT_RENORMALIZE, MG_EUNSTABLE,
+                   MG_EINVAL, MG_ESTATE)
+
+_POT = {"free": MG_POT_FREE, "harmonic": MG_POT_HARMONIC, "morse_repulsion": MG_POT_MORSE_REP,
+        "henon_heiles": MG_POT_HENON_HEILES, "quadratic": MG_POT_QUADRATIC}
+_COMP = {"strang": MG_COMP_STRANG, "suzuki": MG_COMP_SUZUKI, "triple_jump": MG_COMP_TRIPLE_JUMP,
+         "user": MG_COMP_USER}
+_SPLIT = {"TVT": MG_TVT, "VTV": MG_VTV}
+_PREC = {"c128": MG_C128, "c64": MG_C64}
+
+
+def potential_params(kind: str, params: dict, D: int) -> np.ndarray:
+    """Flatten a (kind, params) spec into the mg_set_potential parameter list."""
+    if kind == "free":
+        return np.zeros(0)
+    if kind == "harmonic":
+        s = params.get("s", [0.0] * D)
+        return np.concatenate([np.asarray(params["k"], float), np.asarray(s, float)])
+    if kind == "quadratic":
+        return np.concatenate([np.asarray(params["K"], float).reshape(-1),
+                               np.asarray(params["s"], float)])
+    if kind == "morse_repulsion":
+        return np.array([params["De"], params["a"], params["re"], params["A"], params["b"],
+                         params.get("c", 0.5)], float)
+    if kind == "henon_heiles":
+        return np.array([params["kappa"], params["lam"]], float)
+    raise ValueError(kind)
+
+
+def _torch_stream_and_alloc():
+    try:
+        import torch
+    except ImportError:
+        return None, None
+    if not torch.cuda.is_available():
+        return None, None
+    return torch.cuda.current_stream().cuda_stream, torch
+
+
+class MovingGrid:
+    """One wavepacket on a moving grid (wraps an mg_ctx)."""
+
+    def __init__(self, N, dq, inv_mass, hbar=1.0, precision="c128", use_torch=True):
+        self.D = len(N)
+        self.N = [int(n) for n in N]
+        self.precision = precision
+        lib = L.lib()
+        stream, torch = _torch_stream_and_alloc() if use_torch else (None, None)
+        h = L.C.c_void_p()
+        Narr = np.ascontiguousarray(np.asarray(self.N, dtype=np.int32))
+        st = lib.mg_create(self.D, Narr.ctypes.data_as(L._ip), L.dptr(L.f64(dq, self.D)),
+                           L.dptr(L.f64(inv_mass, self.D)), float(hbar), _PREC[precision],
+                           stream, L.C.byref(h))
+        if st != 0:
+            raise L.MgError(st, "mg_create: " + (lib.mg_last_error(None) or b"").decode())
+        self.h = h
+        self._bufs = []
+        if torch is not None:
+            nb = lib.mg_state_bytes(h)
+            psi = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            self._bufs = [psi, work]
+            L.check(lib.mg_bind_buffers(h, psi.data_ptr(), work.data_ptr()), h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().mg_destroy(self.h)
+            self.h = None
+            self._bufs = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- state -----------------------------------------------------------
+    def set_gaussian(self, q0, p0, sigma):
+        D = self.D
+        L.check(L.lib().mg_set_gaussian(self.h, L.dptr(L.f64(q0, D)), L.dptr(L.f64(p0, D)),
+                                        L.dptr(L.f64(sigma, D))), self.h)
+
+    def set_state(self, psi_phys, q_ctr, p_ctr, t=0.0):
+        a = np.ascontiguousarray(np.asarray(psi_phys, dtype=np.complex128).reshape(self.N))
+        v = a.view(np.float64).reshape(-1)
+        L.check(L.lib().mg_set_state(self.h, L.dptr(v), L.dptr(L.f64(q_ctr, self.D)),
+                                     L.dptr(L.f64(p_ctr, self.D)), float(t)), self.h)
+
+    def get_state(self):
+        psi = np.empty(self.N, dtype=np.complex128)
+        q = np.empty(self.D)
+        p = np.empty(self.D)
+        t = np.empty(1)
+        L.check(L.lib().mg_get_state(self.h, L.dptr(psi.view(np.float64).reshape(-1)), L.dptr(q),
+                                     L.dptr(p), L.dptr(t)), self.h)
+        return psi, q, p, float(t[0])
+
+    # --- model -----------------------------------------------------------
+    def set_potential(self, kind, params):
+        pr = potential_params(kind, params, self.D)
+        L.check(L.lib().mg_set_potential(self.h, _POT[kind], L.dptr(pr) if pr.size else None,
+                                         int(pr.size)), self.h)
+
+    def set_scheme(self, split="TVT", comp="strang", order=2, gammas=None):
+        g = None if gammas is None else L.f64(gammas)
+        L.check(L.lib().mg_set_scheme(self.h, _SPLIT[split], _COMP[comp], int(order),
+                                      L.dptr(g), 0 if g is None else int(g.size)), self.h)
+
+    def set_option(self, option, value):
+        L.check(L.lib().mg_set_option(self.h, int(option), int(value)), self.h)
+
+    # --- propagation -----------------------------------------------------
+    def step(self, dt, nsteps=1):
+        L.check(L.lib().mg_step(self.h, float(dt), int(nsteps)), self.h)
+
+    def observables(self):
+        D = self.D
+        out = np.empty(4 + 4 * D)
+        L.check(L.lib().mg_observables(self.h, L.dptr(out)), self.h)
+        return dict(norm=out[0], q=out[1:1 + D].copy(), p=out[1 + D:1 + 2 * D].copy(),
+                    q_ctr=out[1 + 2 * D:1 + 3 * D].copy(), p_ctr=out[1 + 3 * D:1 + 4 * D].copy(),
+                    Ekin=out[1 + 4 * D], Epot=out[2 + 4 * D], E=out[1 + 4 * D] + out[2 + 4 * D],
+                    t=out[3 + 4 * D])
+
+    def regrid(self, new_q_ctr):
+        L.check(L.lib().mg_regrid(self.h, L.dptr(L.f64(new_q_ctr, self.D))), self.h)
+
+    def profile_read(self, reset=True):
+        n = L.C.c_int64()
+        ms = L.C.c_double()
+        by = L.C.c_double()
+        L.check(L.lib().mg_profile_read(self.h, L.C.byref(n), L.C.byref(ms), L.C.byref(by),
+                                        int(reset)), self.h)
+        return n.value, ms.value, by.value
+
+    def adjoint(self, dt, nsteps, K, window, param_ids):
+        ids = np.ascontiguousarray(np.asarray(param_ids, dtype=np.int32))
+        J = np.empty(1)
+        g = np.empty(len(ids))
+        L.check(L.lib().mg_adjoint(self.h, float(dt), int(nsteps), int(K), L.dptr(L.f64(window, 2)),
+                                   ids.ctypes.data_as(L._ip), int(ids.size), L.dptr(J), L.dptr(g)),
+                self.h)
+        return float(J[0]), g
+
+
+def from_workload(w: dict, precision=None, use_torch=True) -> MovingGrid:
+    """Create, initialise and configure a MovingGrid from a workloads-module dict."""
+    mg = MovingGrid(w["N"], w["dq"], w["inv_mass"], w["hbar"], precision or w["precision"],
+                    use_torch=use_torch)
+    kind, par = w["potential"]
+    mg.set_potential(kind, par)
+    mg.set_scheme(w["split"], w["comp"], w["order"])
+    mg.set_gaussian(w["q0"], w["p0"], w["sigma"])
+    return mg

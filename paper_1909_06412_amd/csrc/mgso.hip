@@ -1,0 +1,1041 @@
+// mgso.hip -- kernels and host runtime behind include/mgso.h (gfx950).
+//
+// Method: Choi & Vanicek, arXiv:1909.06412 (equation numbers count the paper's
+// displayed equations in order of appearance).  See mgso_kernels.h for the
+// arithmetic of one substep and mgso_sweep.h for the tiling.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mgso.h"
+#include "mgso_sweep.h"
+
+using namespace mgk;
+
+#define NTHR 256
+#define MAX_BLOCKS 2048
+
+// ===========================================================================
+// Kernels
+// ===========================================================================
+template <typename T> struct SweepArgs {
+  const PacketGeom* geom;
+  const PacketState* st;
+  const PotDesc* pot;
+  const typename CT<T>::type* src;
+  typename CT<T>::type* dst;
+  Tables<T> tb;
+  double* partials;  // [gridDim.x][MGK_NACC] when epi != 0
+  int si, dir, epi;
+  double h;
+};
+
+// One sweep of one packet over all its tiles (grid-stride over tiles).
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_sweep(SweepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  typedef typename CT<T>::type C;
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  const PacketGeom& G = *a.geom;
+  const SweepDesc& sw = G.sw[a.si];
+  double acc[MGK_NACC];
+#pragma unroll
+  for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
+  for (uint32_t tile = blockIdx.x; tile < sw.ntiles; tile += gridDim.x)
+    process_tile<T, NTHR>(lds, G, a.si, tile, a.src, a.dst, a.tb, a.dir, a.epi, a.h, *a.st, *a.pot, acc, true,
+                          true);
+  if (a.epi) block_reduce<NTHR>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
+}
+
+// Pointwise pass over all points of a packet (standalone potential substep,
+// observables on the position grid, renormalisation).
+template <typename T> struct PointArgs {
+  const PacketGeom* geom;
+  const PacketState* st;
+  const PotDesc* pot;
+  typename CT<T>::type* psi;
+  double* partials;
+  int epi;
+  double h;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_pointwise(PointArgs<T> a) {
+  typedef typename CT<T>::type C;
+  const PacketGeom& G = *a.geom;
+  double acc[MGK_NACC];
+#pragma unroll
+  for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
+  const uint64_t N = G.N_total;
+  for (uint64_t e = (uint64_t)blockIdx.x * NTHR + threadIdx.x; e < N; e += (uint64_t)gridDim.x * NTHR) {
+    int j[MGK_MAXD];
+    decode_index(G, G.D, G.D, (uint32_t)e, 0, 0, j);
+    C x = a.psi[G.off + e];
+    x = epilogue_point<T>(x, j, G, *a.st, *a.pot, a.epi, a.h, acc);
+    if (a.epi & (EPI_V | EPI_SCALE)) a.psi[G.off + e] = x;
+  }
+  __shared__ double red[(NTHR / 64) * MGK_NACC];
+  if (a.epi & (EPI_V | EPI_REDQ | EPI_REDP))
+    block_reduce<NTHR>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, red);
+}
+
+// Finalize modes.
+enum : int {
+  FIN_T = 1,        // <p> -> delta = h m^-1 <p>, q_ctr += delta, then the M tables
+  FIN_V = 2,        // <dV/dq> -> p_ctr -= h <dV/dq>, then the A tables
+  FIN_REGRID = 3,   // delta forced (h = 0), q_ctr += delta, then the M tables
+  FIN_OBSQ = 4,     // store position-grid sums
+  FIN_OBSP = 5,     // store momentum-grid sums
+  FIN_BUILD_A = 6,  // only rebuild the A tables from p_ctr
+  FIN_NORM = 7      // scale = 1/sqrt(sum w) for a following renormalisation pass
+};
+
+template <typename T> struct FinArgs {
+  const PacketGeom* geom;
+  PacketState* st;
+  const double* partials;
+  int nblk;
+  int mode;
+  double h;
+  double forced[MGK_MAXD];
+  typename CT<T>::type* A;
+  typename CT<T>::type* M;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
+  typedef typename CT<T>::type C;
+  const PacketGeom& G = *a.geom;
+  PacketState& st = *a.st;
+  const int D = G.D;
+  const int nacc = D + 2;
+  __shared__ double tot[MGK_NACC];
+  __shared__ double red[(NTHR / 64) * MGK_NACC];
+  if (a.mode != FIN_BUILD_A && a.mode != FIN_REGRID) {
+    double acc[MGK_NACC];
+    for (int k = 0; k < nacc; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < a.nblk; b += NTHR)
+      for (int k = 0; k < nacc; ++k) acc[k] += a.partials[(size_t)b * MGK_NACC + k];
+    block_reduce<NTHR>(acc, nacc, tot, red);
+  }
+  if (threadIdx.x == 0) {
+    if (a.mode == FIN_T || a.mode == FIN_V || a.mode == FIN_NORM)
+      for (int k = 0; k < nacc; ++k) st.last[k] = tot[k];
+    if (a.mode == FIN_T) {
+      const double n = tot[0];
+      bool bad = !(n > 0.0) || !isfinite(n);
+      for (int l = 0; l < D; ++l) {
+        const double pbar = st.p_c[l] + G.ax[l].dp * (tot[1 + l] / n);
+        const double d = a.h * G.ax[l].minv * pbar;
+        if (!isfinite(d) || fabs(d) > 0.5 * G.ax[l].n * G.ax[l].dq) bad = true;
+        st.delta[l] = d;
+        st.q_c[l] += d;
+      }
+      if (bad) st.err = 1;
+    } else if (a.mode == FIN_REGRID) {
+      for (int l = 0; l < D; ++l) {
+        st.delta[l] = a.forced[l];
+        st.q_c[l] += a.forced[l];
+      }
+    } else if (a.mode == FIN_V) {
+      const double n = tot[0];
+      bool bad = !(n > 0.0) || !isfinite(n);
+      for (int l = 0; l < D; ++l) {
+        const double gl = tot[1 + l] / n;
+        if (!isfinite(gl)) bad = true;
+        st.p_c[l] -= a.h * gl;
+      }
+      if (bad) st.err = 1;
+    } else if (a.mode == FIN_OBSQ) {
+      for (int k = 0; k < nacc; ++k) st.obs[k] = tot[k];
+    } else if (a.mode == FIN_OBSP) {
+      for (int k = 0; k < nacc; ++k) st.obs[MGK_NACC + k] = tot[k];
+    } else if (a.mode == FIN_NORM) {
+      st.scale = tot[0] > 0.0 ? 1.0 / sqrt(tot[0]) : 1.0;
+    }
+  }
+  __syncthreads();
+  const double hbar = G.hbar;
+  if (a.mode == FIN_T || a.mode == FIN_REGRID) {
+    const double h = a.mode == FIN_T ? a.h : 0.0;
+    for (int l = 0; l < D; ++l) {
+      const AxisDesc& ax = G.ax[l];
+      for (int k = threadIdx.x; k < ax.n; k += NTHR) {
+        const double p = st.p_c[l] + (double)(k - ax.n / 2) * ax.dp;
+        const double phi = (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / hbar;
+        double s, c;
+        sincos(phi, &s, &c);
+        a.M[ax.tab_off + k] = C{(decltype(C().x))c, (decltype(C().x))(-s)};
+      }
+    }
+  }
+  if (a.mode == FIN_V || a.mode == FIN_BUILD_A) {
+    for (int l = 0; l < D; ++l) {
+      const AxisDesc& ax = G.ax[l];
+      const double inv_sqrt = 1.0 / sqrt((double)ax.n);
+      for (int j = threadIdx.x; j < ax.n; j += NTHR) {
+        const double phi = st.p_c[l] * (double)j * ax.dq / hbar;
+        double s, c;
+        sincos(phi, &s, &c);
+        const double sg = (j & 1) ? -inv_sqrt : inv_sqrt;
+        a.A[ax.tab_off + j] = C{(decltype(C().x))(sg * c), (decltype(C().x))(-sg * s)};
+      }
+    }
+  }
+}
+
+// Initial Gaussian (FP64), one factor per axis, scaled by sqrt(prod dq).
+struct GaussArgs {
+  const PacketGeom* geom;
+  const PacketState* st;
+  double q0[MGK_MAXD], p0[MGK_MAXD], sigma[MGK_MAXD];
+};
+
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_init_gaussian(GaussArgs a, typename CT<T>::type* psi) {
+  typedef typename CT<T>::type C;
+  const PacketGeom& G = *a.geom;
+  const int D = G.D;
+  double lognorm = 0.0;
+  for (int l = 0; l < D; ++l)
+    lognorm += -0.25 * log(M_PI * a.sigma[l] * a.sigma[l]) + 0.5 * log(G.ax[l].dq);
+  for (uint64_t e = (uint64_t)blockIdx.x * NTHR + threadIdx.x; e < G.N_total; e += (uint64_t)gridDim.x * NTHR) {
+    int j[MGK_MAXD];
+    decode_index(G, D, D, (uint32_t)e, 0, 0, j);
+    double re = lognorm, ph = 0.0;
+    for (int l = 0; l < D; ++l) {
+      const double q = a.st->q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq;
+      const double x = q - a.q0[l];
+      re -= x * x / (2.0 * a.sigma[l] * a.sigma[l]);
+      ph += a.p0[l] * x / G.hbar;
+    }
+    const double amp = exp(re);
+    double s, c;
+    sincos(ph, &s, &c);
+    psi[G.off + e] = C{(decltype(C().x))(amp * c), (decltype(C().x))(amp * s)};
+  }
+}
+
+// ===========================================================================
+// Host runtime
+// ===========================================================================
+namespace {
+
+struct Packet {
+  PacketGeom geom;  // host copy
+};
+
+bool is_smooth(int n) {
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  while (n % 5 == 0) n /= 5;
+  return n == 1;
+}
+
+std::vector<int> radices(int n) {
+  std::vector<int> r;
+  while (n % 8 == 0 && n > 8) { r.push_back(8); n /= 8; }
+  if (n % 8 == 0) { r.push_back(8); n /= 8; }
+  while (n % 4 == 0) { r.push_back(4); n /= 4; }
+  while (n % 2 == 0) { r.push_back(2); n /= 2; }
+  while (n % 3 == 0) { r.push_back(3); n /= 3; }
+  while (n % 5 == 0) { r.push_back(5); n /= 5; }
+  return r;
+}
+
+// Build the per-axis passes and the sweep plan of one packet.
+bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, double hbar, int tw_base,
+                std::map<int, int>& tw_offsets, int& tw_total, PacketGeom& G, std::string& err) {
+  memset(&G, 0, sizeof(G));
+  G.D = D;
+  G.hbar = hbar;
+  uint64_t tot = 1;
+  int tab = 0;
+  for (int l = 0; l < D; ++l) {
+    const int n = N[l];
+    if (n < 2 || n % 2 || n > MG_MAX_AXIS || !is_smooth(n)) {
+      err = "N_l must be even, 2.." + std::to_string(MG_MAX_AXIS) + " and of the form 2^a 3^b 5^c";
+      return false;
+    }
+    if (!(dq[l] > 0.0) || !std::isfinite(dq[l]) || !std::isfinite(minv[l])) {
+      err = "dq must be positive and finite, inv_mass finite";
+      return false;
+    }
+    AxisDesc& ax = G.ax[l];
+    ax.n = n;
+    ax.dq = dq[l];
+    ax.dp = 2.0 * M_PI * hbar / (n * dq[l]);
+    ax.minv = minv[l];
+    ax.dn = make_divw(n);
+    ax.tab_off = tab;
+    tab += n;
+    auto it = tw_offsets.find(n);
+    if (it == tw_offsets.end()) {
+      tw_offsets[n] = tw_base + tw_total;
+      ax.tw_off = tw_base + tw_total;
+      tw_total += n;
+    } else {
+      ax.tw_off = it->second;
+    }
+    std::vector<int> rs = radices(n);
+    ax.npass = (int)rs.size();
+    int Ns = 1;
+    for (size_t p = 0; p < rs.size(); ++p) {
+      PassDesc& pd = ax.pass[p];
+      pd.R = (uint16_t)rs[p];
+      pd.Ns = (uint16_t)Ns;
+      pd.tws = (uint16_t)(n / (Ns * rs[p]));
+      pd.dNs = make_div32(Ns);
+      pd.dNbl = make_div32(n / rs[p]);
+      Ns *= rs[p];
+    }
+    tot *= (uint64_t)n;
+  }
+  if (tot > (1ull << 32)) {
+    err = "more than 2^32 grid points";
+    return false;
+  }
+  G.N_total = tot;
+  G.tab_len = tab;
+  // sweeps, from the innermost axis outward
+  const uint32_t RUN = 16;
+  int b = D, ns = 0;
+  while (b > 0) {
+    SweepDesc& s = G.sw[ns];
+    uint64_t I = 1;
+    for (int l = b; l < D; ++l) I *= N[l];
+    int a = b - 1;
+    uint64_t LG = N[a];
+    const uint64_t need = b == D ? 1 : std::min<uint64_t>(I, RUN);
+    while (a > 0 && LG * N[a - 1] * need <= MGK_TMAX) {
+      --a;
+      LG *= N[a];
+    }
+    uint64_t O = 1;
+    for (int l = 0; l < a; ++l) O *= N[l];
+    s.a = a;
+    s.b = b;
+    s.O = (uint32_t)O;
+    s.LG = (uint32_t)LG;
+    s.I = (uint32_t)I;
+    if (b == D) {
+      s.kind = 0;
+      s.ob = (uint32_t)std::min<uint64_t>(O, MGK_TMAX / LG);
+      s.r = 1;
+      s.T = s.ob * s.LG;
+      s.tiles_i = 1;
+      s.ntiles = (uint32_t)((O + s.ob - 1) / s.ob);
+    } else {
+      s.kind = 1;
+      s.ob = 1;
+      s.r = (uint32_t)std::min<uint64_t>(I, MGK_TMAX / LG);
+      s.T = s.LG * s.r;
+      s.tiles_i = (uint32_t)((I + s.r - 1) / s.r);
+      s.ntiles = (uint32_t)(O * s.tiles_i);
+    }
+    s.dLG = make_div32(s.LG);
+    s.dr = make_div32(s.r);
+    s.dtiles_i = make_divw(s.tiles_i);
+    // LDS strides: tile is [ob][N_a..N_{b-1}][r]
+    uint32_t stride = s.kind == 1 ? s.r : 1;
+    for (int l = b - 1; l >= a; --l) {
+      s.S[l - a] = stride;
+      s.dS[l - a] = make_div32(stride);
+      stride *= N[l];
+    }
+    ++ns;
+    b = a;
+  }
+  G.nsweeps = ns;
+  return true;
+}
+
+struct Unit {
+  bool hasT, hasV;
+  double hT, hV;
+};
+
+// Expand a scheme into merged substeps and pair each kinetic substep with the
+// potential substep that follows it.
+std::vector<Unit> lower_scheme(int split, const std::vector<double>& gam, double dt, int64_t nsteps) {
+  std::vector<std::pair<char, double>> subs;
+  for (int64_t s = 0; s < nsteps; ++s)
+    for (double g : gam) {
+      const double h = g * dt;
+      if (split == MG_TVT) {
+        subs.push_back({'T', h / 2});
+        subs.push_back({'V', h});
+        subs.push_back({'T', h / 2});
+      } else {
+        subs.push_back({'V', h / 2});
+        subs.push_back({'T', h});
+        subs.push_back({'V', h / 2});
+      }
+    }
+  std::vector<std::pair<char, double>> merged;
+  for (auto& x : subs) {
+    if (!merged.empty() && merged.back().first == x.first) merged.back().second += x.second;
+    else merged.push_back(x);
+  }
+  std::vector<Unit> units;
+  for (size_t i = 0; i < merged.size(); ++i) {
+    Unit u{false, false, 0.0, 0.0};
+    if (merged[i].first == 'T') {
+      u.hasT = true;
+      u.hT = merged[i].second;
+      if (i + 1 < merged.size() && merged[i + 1].first == 'V') {
+        u.hasV = true;
+        u.hV = merged[i + 1].second;
+        ++i;
+      }
+    } else {
+      u.hasV = true;
+      u.hV = merged[i].second;
+    }
+    units.push_back(u);
+  }
+  return units;
+}
+
+std::vector<double> composition(int comp, int order, const double* user, int nuser, std::string& err) {
+  std::vector<double> g{1.0};
+  if (comp == MG_COMP_USER) {
+    if (!user || nuser < 1) { err = "user gammas missing"; return {}; }
+    std::vector<double> u(user, user + nuser);
+    double s = 0;
+    for (int i = 0; i < nuser; ++i) {
+      s += u[i];
+      if (std::fabs(u[i] - u[nuser - 1 - i]) > 1e-12) { err = "gammas must be palindromic"; return {}; }
+    }
+    if (std::fabs(s - 1.0) > 1e-12) { err = "gammas must sum to one"; return {}; }
+    return u;
+  }
+  if (order < 2 || order > 10 || order % 2) { err = "order must be even, 2..10"; return {}; }
+  if (comp == MG_COMP_STRANG || order == 2) return g;
+  for (int n = 1; n < order / 2; ++n) {
+    std::vector<double> ng;
+    if (comp == MG_COMP_SUZUKI) {
+      const double x = std::pow(4.0, 1.0 / (2 * n + 1));
+      const double a = 1.0 / (4.0 - x);
+      const double c[5] = {a, a, 1.0 - 4.0 * a, a, a};
+      for (double cc : c)
+        for (double gg : g) ng.push_back(cc * gg);
+    } else if (comp == MG_COMP_TRIPLE_JUMP) {
+      const double x = std::pow(2.0, 1.0 / (2 * n + 1));
+      const double a = 1.0 / (2.0 - x);
+      const double c[3] = {a, 1.0 - 2.0 * a, a};
+      for (double cc : c)
+        for (double gg : g) ng.push_back(cc * gg);
+    } else {
+      err = "unknown composition";
+      return {};
+    }
+    g.swap(ng);
+  }
+  return g;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Context
+// ===========================================================================
+struct ProfEntry {
+  hipEvent_t e0, e1;
+  int cls;
+};
+
+struct mg_ctx {
+  int D = 0;
+  mg_precision prec = MG_C128;
+  hipStream_t stream = nullptr;
+  size_t csize = 16;
+  PacketGeom geom{};
+  PacketGeom* d_geom = nullptr;
+  PacketState* d_st = nullptr;
+  PotDesc pot{};
+  PotDesc* d_pot = nullptr;
+  void* d_tw = nullptr;
+  void* d_A = nullptr;
+  void* d_M = nullptr;
+  double* d_part = nullptr;
+  void* psi = nullptr;
+  bool psi_owned = false;
+  void* work = nullptr;
+  bool work_owned = false;
+  bool has_state = false, has_pot = false;
+  int split = MG_TVT;
+  std::vector<double> gam{1.0};
+  int opt_graph = 0, opt_profile = 0, opt_renorm = 0, opt_engine = 0;
+  std::string err;
+  std::vector<ProfEntry> prof_pending;
+  std::map<int, std::pair<int64_t, double>> prof;  // class -> (launches, ms)
+};
+
+static thread_local std::string g_create_err;
+
+static mg_status fail(mg_ctx* c, mg_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail((ctx), MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T> static void build_twiddles(const std::map<int, int>& offs, int total, std::vector<T>& out) {
+  out.assign(2 * (size_t)total, (T)0);
+  for (auto& kv : offs) {
+    const int n = kv.first, off = kv.second;
+    for (int m = 0; m < n; ++m) {
+      const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
+      out[2 * (off + m)] = (T)cosl(ang);
+      out[2 * (off + m) + 1] = (T)sinl(ang);
+    }
+  }
+}
+
+static int grid_for(uint64_t work_items) {
+  uint64_t b = std::max<uint64_t>(1, work_items);
+  return (int)std::min<uint64_t>(b, MAX_BLOCKS);
+}
+
+template <typename T> static Tables<T> tables_of(mg_ctx* c) {
+  typedef typename CT<T>::type C;
+  return Tables<T>{(const C*)c->d_tw, (const C*)c->d_A, (const C*)c->d_M};
+}
+
+template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, double h, int nblk, const double* forced) {
+  typedef typename CT<T>::type C;
+  FinArgs<T> a;
+  memset(&a, 0, sizeof(a));
+  a.geom = c->d_geom;
+  a.st = c->d_st;
+  a.partials = c->d_part;
+  a.nblk = nblk;
+  a.mode = mode;
+  a.h = h;
+  if (forced)
+    for (int l = 0; l < c->D; ++l) a.forced[l] = forced[l];
+  a.A = (C*)c->d_A;
+  a.M = (C*)c->d_M;
+  hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(NTHR), 0, c->stream, a);
+  HIPCHK(c, hipGetLastError());
+  return MG_OK;
+}
+
+// Launch sweep si; returns the number of blocks (for the finalize).
+template <typename T>
+static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk) {
+  typedef typename CT<T>::type C;
+  SweepArgs<T> a;
+  a.geom = c->d_geom;
+  a.st = c->d_st;
+  a.pot = c->d_pot;
+  a.src = (const C*)src;
+  a.dst = (C*)dst;
+  a.tb = tables_of<T>(c);
+  a.partials = c->d_part;
+  a.si = si;
+  a.dir = dir;
+  a.epi = epi;
+  a.h = h;
+  const int grid = grid_for(c->geom.sw[si].ntiles);
+  *nblk = grid;
+  const size_t lds = (size_t)MGK_TMAX * sizeof(C);
+  ProfEntry pe{};
+  if (c->opt_profile) {
+    HIPCHK(c, hipEventCreate(&pe.e0));
+    HIPCHK(c, hipEventCreate(&pe.e1));
+    HIPCHK(c, hipEventRecord(pe.e0, c->stream));
+  }
+  hipLaunchKernelGGL(k_sweep<T>, dim3(grid), dim3(NTHR), lds, c->stream, a);
+  HIPCHK(c, hipGetLastError());
+  if (c->opt_profile) {
+    HIPCHK(c, hipEventRecord(pe.e1, c->stream));
+    pe.cls = si * 64 + dir * 32 + epi;
+    c->prof_pending.push_back(pe);
+  }
+  return MG_OK;
+}
+
+template <typename T> static mg_status launch_pointwise(mg_ctx* c, int epi, double h, int* nblk) {
+  typedef typename CT<T>::type C;
+  PointArgs<T> a;
+  a.geom = c->d_geom;
+  a.st = c->d_st;
+  a.pot = c->d_pot;
+  a.psi = (C*)c->psi;
+  a.partials = c->d_part;
+  a.epi = epi;
+  a.h = h;
+  const int grid = grid_for((c->geom.N_total + NTHR - 1) / NTHR);
+  *nblk = grid;
+  hipLaunchKernelGGL(k_pointwise<T>, dim3(grid), dim3(NTHR), 0, c->stream, a);
+  HIPCHK(c, hipGetLastError());
+  return MG_OK;
+}
+
+// Forward transform of src into dst (dst may equal src); the last sweep reduces
+// the momentum moments with epilogue `epi_last`.
+template <typename T>
+static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last) {
+  const int ns = c->geom.nsweeps;
+  for (int s = 0; s < ns; ++s) {
+    int nb;
+    mg_status r = launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb);
+    if (r) return r;
+    if (s == ns - 1) *nblk_last = nb;
+  }
+  return MG_OK;
+}
+
+template <typename T>
+static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last) {
+  const int ns = c->geom.nsweeps;
+  for (int s = ns - 1; s >= 0; --s) {
+    int nb;
+    mg_status r = launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb);
+    if (r) return r;
+    if (s == 0) *nblk_last = nb;
+  }
+  return MG_OK;
+}
+
+template <typename T> static mg_status run_unit(mg_ctx* c, const Unit& u) {
+  mg_status r;
+  int nb = 0;
+  if (u.hasT) {
+    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb))) return r;
+    if ((r = launch_finalize<T>(c, FIN_T, u.hT, nb, nullptr))) return r;
+    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb))) return r;
+    if (u.hasV && (r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
+  } else if (u.hasV) {
+    if ((r = launch_pointwise<T>(c, EPI_V, u.hV, &nb))) return r;
+    if ((r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
+  }
+  if (u.hasV && c->opt_renorm) {
+    if ((r = launch_pointwise<T>(c, EPI_REDQ, 0.0, &nb))) return r;
+    if ((r = launch_finalize<T>(c, FIN_NORM, 0.0, nb, nullptr))) return r;
+    if ((r = launch_pointwise<T>(c, EPI_SCALE, 0.0, &nb))) return r;
+  }
+  return MG_OK;
+}
+
+static mg_status collect_profile(mg_ctx* c) {
+  for (auto& pe : c->prof_pending) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, pe.e0, pe.e1));
+    auto& e = c->prof[pe.cls];
+    e.first += 1;
+    e.second += ms;
+    hipEventDestroy(pe.e0);
+    hipEventDestroy(pe.e1);
+  }
+  c->prof_pending.clear();
+  return MG_OK;
+}
+
+template <typename T> static mg_status step_impl(mg_ctx* c, double dt, int64_t nsteps) {
+  mg_status r;
+  if ((r = launch_finalize<T>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+  std::vector<Unit> units = lower_scheme(c->split, c->gam, dt, nsteps);
+  for (const Unit& u : units)
+    if ((r = run_unit<T>(c, u))) return r;
+  return MG_OK;
+}
+
+static mg_status sync_and_check(mg_ctx* c) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->opt_profile) {
+    mg_status r = collect_profile(c);
+    if (r) return r;
+  }
+  int32_t err = 0;
+  HIPCHK(c, hipMemcpy(&err, &c->d_st->err, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (err) {
+    c->has_state = false;
+    return fail(c, MG_EUNSTABLE,
+                "non-finite moments or a grid shift beyond half the grid span (Verlet instability of the centres)");
+  }
+  return MG_OK;
+}
+
+static mg_status ensure_psi(mg_ctx* c) {
+  if (!c->psi) {
+    HIPCHK(c, hipMalloc(&c->psi, mg_state_bytes(c)));
+    c->psi_owned = true;
+  }
+  return MG_OK;
+}
+
+static mg_status ensure_work(mg_ctx* c) {
+  if (!c->work) {
+    HIPCHK(c, hipMalloc(&c->work, mg_workspace_bytes(c)));
+    c->work_owned = true;
+  }
+  return MG_OK;
+}
+
+static mg_status upload_state_scalars(mg_ctx* c, const double* q, const double* p, double t) {
+  PacketState st;
+  memset(&st, 0, sizeof(st));
+  for (int l = 0; l < c->D; ++l) {
+    st.q_c[l] = q[l];
+    st.p_c[l] = p[l];
+  }
+  st.t = t;
+  st.scale = 1.0;
+  HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
+  return MG_OK;
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv_mass, double hbar,
+                    mg_precision prec, void* hip_stream, mg_ctx** out) {
+  if (!out) return MG_EINVAL;
+  *out = nullptr;
+  if (D < 1 || D > MG_MAX_DIM || !N || !dq || !inv_mass || !(hbar > 0.0) || (prec != MG_C128 && prec != MG_C64))
+    return MG_EINVAL;
+  mg_ctx* c = new mg_ctx();
+  c->D = D;
+  c->prec = prec;
+  c->stream = (hipStream_t)hip_stream;
+  c->csize = prec == MG_C64 ? 8 : 16;
+  std::map<int, int> tw_offs;
+  int tw_total = 0;
+  if (!build_geom(D, N, dq, inv_mass, hbar, 0, tw_offs, tw_total, c->geom, c->err)) {
+    g_create_err = c->err;
+    delete c;
+    return MG_EINVAL;
+  }
+  c->geom.off = 0;
+  c->pot.kind = MG_POT_FREE;
+  c->pot.D = D;
+  hipError_t e = hipSuccess;
+  const char* where = "hipMalloc";
+  e = hipMalloc(&c->d_geom, sizeof(PacketGeom));
+  if (e == hipSuccess) e = hipMalloc(&c->d_st, sizeof(PacketState));
+  if (e == hipSuccess) e = hipMalloc(&c->d_pot, sizeof(PotDesc));
+  if (e == hipSuccess) e = hipMalloc(&c->d_tw, (size_t)tw_total * c->csize);
+  if (e == hipSuccess) e = hipMalloc(&c->d_A, (size_t)c->geom.tab_len * c->csize);
+  if (e == hipSuccess) e = hipMalloc(&c->d_M, (size_t)c->geom.tab_len * c->csize);
+  if (e == hipSuccess) e = hipMalloc(&c->d_part, (size_t)MAX_BLOCKS * MGK_NACC * sizeof(double));
+  if (e == hipSuccess) where = "hipMemcpy";
+  if (e == hipSuccess) e = hipMemcpy(c->d_geom, &c->geom, sizeof(PacketGeom), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(c->d_pot, &c->pot, sizeof(PotDesc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(c->d_st, 0, sizeof(PacketState));
+  if (e == hipSuccess) {
+    if (prec == MG_C64) {
+      std::vector<float> tw;
+      build_twiddles<float>(tw_offs, tw_total, tw);
+      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);
+    } else {
+      std::vector<double> tw;
+      build_twiddles<double>(tw_offs, tw_total, tw);
+      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+    }
+  }
+  if (e != hipSuccess) {
+    g_create_err = std::string(where) + ": " + hipGetErrorString(e);
+    mg_destroy(c);
+    return e == hipErrorOutOfMemory ? MG_ENOMEM : MG_EDEVICE;
+  }
+  *out = c;
+  return MG_OK;
+}
+
+void mg_destroy(mg_ctx* c) {
+  if (!c) return;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  else hipDeviceSynchronize();
+  for (auto& pe : c->prof_pending) {
+    hipEventDestroy(pe.e0);
+    hipEventDestroy(pe.e1);
+  }
+  if (c->psi_owned) hipFree(c->psi);
+  if (c->work_owned) hipFree(c->work);
+  hipFree(c->d_geom);
+  hipFree(c->d_st);
+  hipFree(c->d_pot);
+  hipFree(c->d_tw);
+  hipFree(c->d_A);
+  hipFree(c->d_M);
+  hipFree(c->d_part);
+  delete c;
+}
+
+size_t mg_state_bytes(const mg_ctx* c) { return c ? (size_t)c->geom.N_total * c->csize : 0; }
+size_t mg_workspace_bytes(const mg_ctx* c) { return c ? (size_t)c->geom.N_total * c->csize : 0; }
+void* mg_state_ptr(mg_ctx* c) { return c ? c->psi : nullptr; }
+
+mg_status mg_bind_buffers(mg_ctx* c, void* psi_dev, void* work_dev) {
+  if (!c || !psi_dev) return fail(c, MG_EINVAL, "psi_dev is NULL");
+  if (((uintptr_t)psi_dev & 255) || ((uintptr_t)work_dev & 255)) return fail(c, MG_EINVAL, "buffers must be 256-byte aligned");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->psi_owned) hipFree(c->psi);
+  if (c->work_owned && work_dev) hipFree(c->work);
+  c->psi = psi_dev;
+  c->psi_owned = false;
+  if (work_dev) {
+    c->work = work_dev;
+    c->work_owned = false;
+  }
+  c->has_state = false;
+  return MG_OK;
+}
+
+mg_status mg_set_gaussian(mg_ctx* c, const double* q0, const double* p0, const double* sigma) {
+  if (!c || !q0 || !p0 || !sigma) return fail(c, MG_EINVAL, "null argument");
+  for (int l = 0; l < c->D; ++l)
+    if (!(sigma[l] > 0.0) || !std::isfinite(q0[l]) || !std::isfinite(p0[l]))
+      return fail(c, MG_EINVAL, "sigma must be positive, q0/p0 finite");
+  mg_status r;
+  if ((r = ensure_psi(c))) return r;
+  if ((r = upload_state_scalars(c, q0, p0, 0.0))) return r;
+  GaussArgs a;
+  memset(&a, 0, sizeof(a));
+  a.geom = c->d_geom;
+  a.st = c->d_st;
+  for (int l = 0; l < c->D; ++l) {
+    a.q0[l] = q0[l];
+    a.p0[l] = p0[l];
+    a.sigma[l] = sigma[l];
+  }
+  const int grid = grid_for((c->geom.N_total + NTHR - 1) / NTHR);
+  if (c->prec == MG_C64)
+    hipLaunchKernelGGL(k_init_gaussian<float>, dim3(grid), dim3(NTHR), 0, c->stream, a, (float2*)c->psi);
+  else
+    hipLaunchKernelGGL(k_init_gaussian<double>, dim3(grid), dim3(NTHR), 0, c->stream, a, (double2*)c->psi);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_state = true;
+  return MG_OK;
+}
+
+mg_status mg_set_state(mg_ctx* c, const double* psi_phys, const double* q, const double* p, double t) {
+  if (!c || !psi_phys || !q || !p) return fail(c, MG_EINVAL, "null argument");
+  mg_status r;
+  if ((r = ensure_psi(c))) return r;
+  double sc = 1.0;
+  for (int l = 0; l < c->D; ++l) sc *= c->geom.ax[l].dq;
+  sc = std::sqrt(sc);
+  const size_t n2 = 2 * (size_t)c->geom.N_total;
+  if (c->prec == MG_C64) {
+    std::vector<float> h(n2);
+    for (size_t i = 0; i < n2; ++i) h[i] = (float)(psi_phys[i] * sc);
+    HIPCHK(c, hipMemcpyAsync(c->psi, h.data(), n2 * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::vector<double> h(n2);
+    for (size_t i = 0; i < n2; ++i) h[i] = psi_phys[i] * sc;
+    HIPCHK(c, hipMemcpyAsync(c->psi, h.data(), n2 * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if ((r = upload_state_scalars(c, q, p, t))) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_state = true;
+  return MG_OK;
+}
+
+mg_status mg_get_state(mg_ctx* c, double* psi_phys, double* q, double* p, double* t) {
+  if (!c) return MG_EINVAL;
+  if (!c->psi) return fail(c, MG_ESTATE, "no state");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  PacketState st;
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  if (q)
+    for (int l = 0; l < c->D; ++l) q[l] = st.q_c[l];
+  if (p)
+    for (int l = 0; l < c->D; ++l) p[l] = st.p_c[l];
+  if (t) *t = st.t;
+  if (psi_phys) {
+    double sc = 1.0;
+    for (int l = 0; l < c->D; ++l) sc *= c->geom.ax[l].dq;
+    sc = 1.0 / std::sqrt(sc);
+    const size_t n2 = 2 * (size_t)c->geom.N_total;
+    if (c->prec == MG_C64) {
+      std::vector<float> h(n2);
+      HIPCHK(c, hipMemcpy(h.data(), c->psi, n2 * sizeof(float), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n2; ++i) psi_phys[i] = (double)h[i] * sc;
+    } else {
+      HIPCHK(c, hipMemcpy(psi_phys, c->psi, n2 * sizeof(double), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n2; ++i) psi_phys[i] *= sc;
+    }
+  }
+  return MG_OK;
+}
+
+mg_status mg_set_potential(mg_ctx* c, mg_pot kind, const double* params, int np) {
+  if (!c) return MG_EINVAL;
+  PotDesc P;
+  memset(&P, 0, sizeof(P));
+  P.kind = kind;
+  P.D = c->D;
+  const int D = c->D;
+  int need = -1;
+  switch (kind) {
+    case MG_POT_FREE: need = 0; break;
+    case MG_POT_HARMONIC: need = 2 * D; break;
+    case MG_POT_MORSE_REP: need = 6; if (D > 2) return fail(c, MG_EINVAL, "Morse+repulsion needs D <= 2"); break;
+    case MG_POT_HENON_HEILES: need = 2; break;
+    case MG_POT_QUADRATIC: need = D * D + D; if (D > 4) return fail(c, MG_EINVAL, "quadratic needs D <= 4"); break;
+    default: return fail(c, MG_EINVAL, "unknown potential kind");
+  }
+  if (np != need || (need > 0 && !params)) return fail(c, MG_EINVAL, "wrong number of potential parameters");
+  for (int i = 0; i < np; ++i) {
+    if (!std::isfinite(params[i])) return fail(c, MG_EINVAL, "non-finite potential parameter");
+    P.p[i] = params[i];
+  }
+  c->pot = P;
+  HIPCHK(c, hipMemcpyAsync(c->d_pot, &c->pot, sizeof(PotDesc), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->has_pot = true;
+  return MG_OK;
+}
+
+mg_status mg_set_scheme(mg_ctx* c, mg_split split, mg_comp comp, int order, const double* gammas, int ns) {
+  if (!c) return MG_EINVAL;
+  if (split != MG_TVT && split != MG_VTV) return fail(c, MG_EINVAL, "unknown split");
+  std::string e;
+  std::vector<double> g = composition(comp, order, gammas, ns, e);
+  if (g.empty()) return fail(c, MG_EINVAL, e);
+  c->split = split;
+  c->gam = g;
+  return MG_OK;
+}
+
+mg_status mg_step(mg_ctx* c, double dt, int64_t nsteps) {
+  if (!c) return MG_EINVAL;
+  if (!c->has_state) return fail(c, MG_ESTATE, "no valid state (set_gaussian / set_state first)");
+  if (!std::isfinite(dt) || nsteps < 0) return fail(c, MG_EINVAL, "bad dt or nsteps");
+  if (nsteps == 0) return MG_OK;
+  mg_status r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
+  if (r) return r;
+  if ((r = sync_and_check(c))) return r;
+  // advance t on the host side of the state (device copy kept consistent)
+  PacketState st;
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  st.t += dt * (double)nsteps;
+  HIPCHK(c, hipMemcpy(&c->d_st->t, &st.t, sizeof(double), hipMemcpyHostToDevice));
+  return MG_OK;
+}
+
+mg_status mg_observables(mg_ctx* c, double* out) {
+  if (!c || !out) return MG_EINVAL;
+  if (!c->has_state) return fail(c, MG_ESTATE, "no valid state");
+  mg_status r;
+  if ((r = ensure_work(c))) return r;
+  int nb = 0;
+  if (c->prec == MG_C64) {
+    if ((r = launch_finalize<float>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+    if ((r = launch_pointwise<float>(c, EPI_REDQ, 0.0, &nb))) return r;
+    if ((r = launch_finalize<float>(c, FIN_OBSQ, 0.0, nb, nullptr))) return r;
+    if ((r = forward_transform<float>(c, c->psi, c->work, EPI_REDP | EPI_EKIN, &nb))) return r;
+    if ((r = launch_finalize<float>(c, FIN_OBSP, 0.0, nb, nullptr))) return r;
+  } else {
+    if ((r = launch_finalize<double>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+    if ((r = launch_pointwise<double>(c, EPI_REDQ, 0.0, &nb))) return r;
+    if ((r = launch_finalize<double>(c, FIN_OBSQ, 0.0, nb, nullptr))) return r;
+    if ((r = forward_transform<double>(c, c->psi, c->work, EPI_REDP | EPI_EKIN, &nb))) return r;
+    if ((r = launch_finalize<double>(c, FIN_OBSP, 0.0, nb, nullptr))) return r;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  PacketState st;
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  const int D = c->D;
+  const double* sq = st.obs;
+  const double* sp = st.obs + MGK_NACC;
+  out[0] = sq[0];
+  for (int l = 0; l < D; ++l) {
+    out[1 + l] = st.q_c[l] + c->geom.ax[l].dq * sq[1 + l] / sq[0];
+    out[1 + D + l] = st.p_c[l] + c->geom.ax[l].dp * sp[1 + l] / sp[0];
+    out[1 + 2 * D + l] = st.q_c[l];
+    out[1 + 3 * D + l] = st.p_c[l];
+  }
+  out[1 + 4 * D] = sp[D + 1] / sp[0];
+  out[2 + 4 * D] = sq[D + 1] / sq[0];
+  out[3 + 4 * D] = st.t;
+  return MG_OK;
+}
+
+mg_status mg_regrid(mg_ctx* c, const double* new_q) {
+  if (!c || !new_q) return MG_EINVAL;
+  if (!c->has_state) return fail(c, MG_ESTATE, "no valid state");
+  PacketState st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  double d[MGK_MAXD];
+  for (int l = 0; l < c->D; ++l) d[l] = new_q[l] - st.q_c[l];
+  mg_status r;
+  int nb = 0;
+  if (c->prec == MG_C64) {
+    if ((r = launch_finalize<float>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+    if ((r = forward_transform<float>(c, c->psi, c->psi, 0, &nb))) return r;
+    if ((r = launch_finalize<float>(c, FIN_REGRID, 0.0, 0, d))) return r;
+    if ((r = inverse_transform<float>(c, c->psi, 0, 0.0, &nb))) return r;
+  } else {
+    if ((r = launch_finalize<double>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+    if ((r = forward_transform<double>(c, c->psi, c->psi, 0, &nb))) return r;
+    if ((r = launch_finalize<double>(c, FIN_REGRID, 0.0, 0, d))) return r;
+    if ((r = inverse_transform<double>(c, c->psi, 0, 0.0, &nb))) return r;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // the forced shift lands exactly on new_q
+  HIPCHK(c, hipMemcpy(c->d_st->q_c, new_q, sizeof(double) * c->D, hipMemcpyHostToDevice));
+  return MG_OK;
+}
+
+mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
+  if (!c) return MG_EINVAL;
+  switch (option) {
+    case MG_OPT_ENGINE: if (value < 0 || value > 2) return fail(c, MG_EINVAL, "engine 0..2"); c->opt_engine = (int)value; break;
+    case MG_OPT_GRAPH: c->opt_graph = value != 0; break;
+    case MG_OPT_PROFILE: c->opt_profile = value != 0; break;
+    case MG_OPT_RENORMALIZE: c->opt_renorm = value != 0; break;
+    default: return fail(c, MG_EINVAL, "unknown option");
+  }
+  return MG_OK;
+}
+
+mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double* bytes, int reset) {
+  if (!c) return MG_EINVAL;
+  int best = -1;
+  double best_ms = -1;
+  for (auto& kv : c->prof)
+    if (kv.second.second > best_ms) {
+      best_ms = kv.second.second;
+      best = kv.first;
+    }
+  if (launches) *launches = best < 0 ? 0 : c->prof[best].first;
+  if (total_ms) *total_ms = best < 0 ? 0.0 : best_ms;
+  if (bytes) *bytes = 2.0 * (double)c->geom.N_total * (double)c->csize;
+  if (reset) c->prof.clear();
+  return MG_OK;
+}
+
+const char* mg_last_error(const void* p) {
+  if (!p) return g_create_err.empty() ? "null context" : g_create_err.c_str();
+  return ((const mg_ctx*)p)->err.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Entry points completed in mgso_batch.hip / mgso_adjoint.hip
+// ===========================================================================
+#include "mgso_batch.inc"

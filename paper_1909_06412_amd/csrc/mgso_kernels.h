@@ -1,0 +1,389 @@
+// mgso_kernels.h -- gfx950 device code of the moving-grid split-operator step.
+//
+// Method: Choi & Vanicek, arXiv:1909.06412 (equation numbers count the paper's
+// displayed equations in order of appearance).  One TVT stage is, per packet,
+//
+//   kinetic substep U_T,adpt(h)  (Sec. II.G.2, Eq. (55) with Eqs. (49), (52)):
+//     X = DFT[A c] / sqrt(N),  A_J = prod_l (-1)^{j_l} exp(-i p_ctr,l j_l dq_l / hbar)
+//     <p> = p_ctr + dp * sum |X|^2 (k - N/2) / sum |X|^2,   delta = h m^-1 <p>
+//     c  <- conj(A) IDFT[M X] / sqrt(N),  M_K = exp(-i [h T(p^K) - delta . p^K] / hbar)
+//     q_ctr += delta
+//   (the centre-dependent post-phase and constant of the paper's f(q,p) in Eq. (19)
+//   cancel between f~(q_h, p) and f(q, p) except for the delta . p^K term kept in M)
+//
+//   potential substep U_V,adpt(h)  (Sec. II.G.1, Eqs. (45)-(47)):
+//     p_ctr -= h sum |c|^2 dV/dq(q^J) / sum |c|^2,   c <- c exp(-i h V(q^J) / hbar)
+//
+// A, M are separable, so each axis' factor is applied inside the sweep that
+// transforms that axis, from per-axis tables built in FP64 and rounded once.
+// Reductions are FP64, per thread -> wave -> workgroup -> fixed-order finalize.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "mgso_common.h"
+
+namespace mgk {
+
+template <typename T> struct CT;
+template <> struct CT<float> { typedef float2 type; };
+template <> struct CT<double> { typedef double2 type; };
+
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
+  return C{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
+  return C{a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// a * (-i) when fwd, a * (+i) when inverse
+template <typename C> __device__ __forceinline__ C rot(C a, bool inv) {
+  return inv ? C{-a.y, a.x} : C{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers: forward sign exp(-2 pi i nk/R), inverse exp(+...)
+// ---------------------------------------------------------------------------
+template <typename C> __device__ __forceinline__ void dft2(C* v) {
+  C a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename C> __device__ __forceinline__ void dft4(C* v, bool inv) {
+  C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  C t2 = cadd(v[1], v[3]), t3 = rot(csub(v[1], v[3]), inv);
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft8(C* v, bool inv) {
+  const T h = (T)0.70710678118654752440084436210485;
+  C b[4], c[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    b[n] = cadd(v[n], v[n + 4]);
+    c[n] = csub(v[n], v[n + 4]);
+  }
+  // c_n *= w8^n, w8 = exp(-+ i pi / 4)
+  {
+    C x = c[1];
+    c[1] = inv ? C{h * (x.x - x.y), h * (x.x + x.y)} : C{h * (x.x + x.y), h * (x.y - x.x)};
+    c[2] = rot(c[2], inv);
+    x = c[3];
+    c[3] = inv ? C{-h * (x.x + x.y), h * (x.x - x.y)} : C{h * (x.y - x.x), -h * (x.x + x.y)};
+  }
+  dft4(b, inv);
+  dft4(c, inv);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    v[2 * m] = b[m];
+    v[2 * m + 1] = c[m];
+  }
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft3(C* v, bool inv) {
+  const T s = (T)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+  C t = cadd(v[1], v[2]);
+  C u = csub(v[1], v[2]);
+  C y0 = cadd(v[0], t);
+  C m = C{v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y};
+  C su = rot(C{s * u.x, s * u.y}, inv);  // -+ i s u
+  v[0] = y0;
+  v[1] = cadd(m, su);
+  v[2] = csub(m, su);
+}
+
+template <typename T, typename C> __device__ __forceinline__ void dft5(C* v, bool inv) {
+  const T c1 = (T)0.30901699437494742410229341718282;   // cos(2 pi / 5)
+  const T c2 = (T)-0.80901699437494742410229341718282;  // cos(4 pi / 5)
+  const T s1 = (T)0.95105651629515357211643933337938;   // sin(2 pi / 5)
+  const T s2 = (T)0.58778525229247312916870595463907;   // sin(4 pi / 5)
+  C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+  C u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
+  C y0 = C{v[0].x + t1.x + t2.x, v[0].y + t1.y + t2.y};
+  C m1 = C{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
+  C m2 = C{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
+  C n1 = rot(C{s1 * u1.x + s2 * u2.x, s1 * u1.y + s2 * u2.y}, inv);
+  C n2 = rot(C{s2 * u1.x - s1 * u2.x, s2 * u1.y - s1 * u2.y}, inv);
+  v[0] = y0;
+  v[1] = cadd(m1, n1);
+  v[4] = csub(m1, n1);
+  v[2] = cadd(m2, n2);
+  v[3] = csub(m2, n2);
+}
+
+template <typename T, int R, typename C> __device__ __forceinline__ void dftR(C* v, bool inv) {
+  if constexpr (R == 2) dft2(v);
+  else if constexpr (R == 3) dft3<T>(v, inv);
+  else if constexpr (R == 4) dft4(v, inv);
+  else if constexpr (R == 5) dft5<T>(v, inv);
+  else if constexpr (R == 8) dft8<T>(v, inv);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass of radix R over every line of one axis of the LDS tile.
+// Reads all of a thread's butterflies into registers, barrier, writes them back.
+// pre (first pass) multiplies inputs by a per-axis table at the natural index;
+// post (last pass) multiplies outputs by a per-axis table (or its conjugate).
+// ---------------------------------------------------------------------------
+template <typename T, int R, int NTHR>
+__device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_t Tn, uint32_t n,
+                                              uint32_t S, Div32 dS, const PassDesc& pd, bool inv,
+                                              const typename CT<T>::type* __restrict__ tw,
+                                              const typename CT<T>::type* __restrict__ pre,
+                                              const typename CT<T>::type* __restrict__ post,
+                                              bool post_conj) {
+  typedef typename CT<T>::type C;
+  constexpr int MB = (MGK_TMAX + R * NTHR - 1) / (R * NTHR);
+  const uint32_t nbl = n / R;
+  const uint32_t nb = Tn / R;
+  const uint32_t Ns = pd.Ns;
+  C v[MB][R];
+  uint32_t base[MB], jj[MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const uint32_t bf = threadIdx.x + m * NTHR;
+    if (bf < nb) {
+      uint32_t b0, j;
+      bfly_index(bf, n, S, dS, pd.dNbl, &b0, &j);
+      base[m] = b0;
+      jj[m] = j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[m][r] = lds[b0 + (j + r * nbl) * S];
+      if (pre) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[m][r] = cmul(v[m][r], pre[j + r * nbl]);
+      }
+      if (Ns > 1) {
+        const uint32_t k = j - div32(j, pd.dNs) * Ns;
+        const uint32_t step = k * pd.tws;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          C w = tw[r * step];
+          v[m][r] = inv ? cmulc(v[m][r], w) : cmul(v[m][r], w);
+        }
+      }
+      dftR<T, R>(v[m], inv);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    const uint32_t bf = threadIdx.x + m * NTHR;
+    if (bf < nb) {
+      const uint32_t j = jj[m];
+      const uint32_t k = j - div32(j, pd.dNs) * Ns;
+      const uint32_t o0 = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t p = o0 + r * Ns;
+        C x = v[m][r];
+        if (post) x = post_conj ? cmulc(x, post[p]) : cmul(x, post[p]);
+        lds[base[m] + p * S] = x;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// FFT of every line of axis `ax` in the tile (all passes of that axis).
+template <typename T, int NTHR>
+__device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_t Tn,
+                                              const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
+                                              const typename CT<T>::type* tw,
+                                              const typename CT<T>::type* pre,
+                                              const typename CT<T>::type* post, bool post_conj) {
+  const int np = ax.npass;
+  for (int p = 0; p < np; ++p) {
+    const PassDesc& pd = ax.pass[p];
+    const typename CT<T>::type* pr = p == 0 ? pre : nullptr;
+    const typename CT<T>::type* po = p == np - 1 ? post : nullptr;
+    switch (pd.R) {
+      case 2: stockham_pass<T, 2, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 3: stockham_pass<T, 3, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 4: stockham_pass<T, 4, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 5: stockham_pass<T, 5, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      default: stockham_pass<T, 8, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Potentials (FP64): value and gradient at one grid point.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double* q, double* g) {
+  double V = 0.0;
+  switch (P.kind) {
+    case 1: {  // harmonic: k[D], s[D]
+      for (int l = 0; l < D; ++l) {
+        const double x = q[l] - P.p[D + l];
+        V += 0.5 * P.p[l] * x * x;
+        if (g) g[l] = P.p[l] * x;
+      }
+      break;
+    }
+    case 2: {  // Morse + repulsion: De, a, re, A, b, c
+      const double e = exp(-P.p[1] * (q[0] - P.p[2]));
+      V = P.p[0] * (1.0 - e) * (1.0 - e);
+      double g0 = 2.0 * P.p[0] * P.p[1] * e * (1.0 - e);
+      if (D > 1) {
+        const double rep = P.p[3] * exp(-P.p[4] * (q[1] - P.p[5] * q[0]));
+        V += rep;
+        g0 += P.p[4] * P.p[5] * rep;
+        if (g) g[1] = -P.p[4] * rep;
+      }
+      if (g) g[0] = g0;
+      break;
+    }
+    case 3: {  // Henon-Heiles: kappa, lam
+      const double ka = P.p[0], la = P.p[1];
+      for (int l = 0; l < D; ++l) {
+        V += 0.5 * ka * q[l] * q[l];
+        if (g) g[l] = ka * q[l];
+      }
+      for (int l = 0; l + 1 < D; ++l) {
+        const double a = q[l], b = q[l + 1];
+        V += la * (a * a * b - b * b * b / 3.0);
+        if (g) {
+          g[l] += 2.0 * la * a * b;
+          g[l + 1] += la * (a * a - b * b);
+        }
+      }
+      break;
+    }
+    case 4: {  // quadratic: K[D*D], s[D]  (D <= 4)
+      double x[4];
+      for (int l = 0; l < D; ++l) x[l] = q[l] - P.p[D * D + l];
+      for (int a = 0; a < D; ++a) {
+        double row = 0.0;
+        for (int b = 0; b < D; ++b) row += P.p[a * D + b] * x[b];
+        V += 0.5 * x[a] * row;
+        if (g) g[a] = row;
+      }
+      break;
+    }
+    default:
+      if (g)
+        for (int l = 0; l < D; ++l) g[l] = 0.0;
+      break;
+  }
+  return V;
+}
+
+// exp(-i phi) with phi in FP64, rounded to the storage precision.
+template <typename T> __device__ __forceinline__ typename CT<T>::type phase_of(double phi);
+template <> __device__ __forceinline__ float2 phase_of<float>(double phi) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double r = phi - two_pi * rint(phi * (1.0 / two_pi));
+  float s, c;
+  sincosf((float)r, &s, &c);
+  return float2{c, -s};
+}
+template <> __device__ __forceinline__ double2 phase_of<double>(double phi) {
+  double s, c;
+  sincos(phi, &s, &c);
+  return double2{c, -s};
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup reduction of nacc FP64 values to out[0..nacc) (fixed order).
+// ---------------------------------------------------------------------------
+// `red` is LDS scratch of (NTHR/64) * MGK_NACC doubles (the caller's tile buffer
+// once the tile work is done).
+template <int NTHR>
+__device__ __forceinline__ void block_reduce(double* acc, int nacc, double* out, double* red) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  for (int k = 0; k < nacc; ++k) {
+    double v = acc[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wv * MGK_NACC + k] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nacc) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NTHR / 64; ++w) s += red[w * MGK_NACC + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Decode the multi-index of a point from (outer, group, inner) parts of a sweep.
+__device__ __forceinline__ void decode_index(const PacketGeom& G, int a, int b, uint32_t o, uint32_t g,
+                                             uint32_t i, int* j) {
+  const int D = G.D;
+  for (int l = D - 1; l >= b; --l) {
+    const uint32_t qq = divw(i, G.ax[l].dn);
+    j[l] = (int)(i - qq * (uint32_t)G.ax[l].n);
+    i = qq;
+  }
+  for (int l = b - 1; l >= a; --l) {
+    const uint32_t qq = divw(g, G.ax[l].dn);
+    j[l] = (int)(g - qq * (uint32_t)G.ax[l].n);
+    g = qq;
+  }
+  for (int l = a - 1; l >= 0; --l) {
+    const uint32_t qq = divw(o, G.ax[l].dn);
+    j[l] = (int)(o - qq * (uint32_t)G.ax[l].n);
+    o = qq;
+  }
+}
+
+// Epilogue modes of a sweep / pointwise pass (bit flags).
+enum : int {
+  EPI_REDP = 1,    // sums w, w (k_l - N_l/2)                      (momentum moments)
+  EPI_EKIN = 2,    // + sum w T(p^K)                                (observables)
+  EPI_V = 4,       // potential substep: phase exp(-i h V / hbar) and sums w, w dV/dq_l
+  EPI_REDQ = 8,    // sums w, w (j_l - N_l/2), w V(q^J)             (observables)
+  EPI_SCALE = 16   // multiply by PacketState.scale
+};
+
+// Pointwise work on one element with full multi-index j; returns the new value.
+template <typename T>
+__device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::type x, const int* j,
+                                                               const PacketGeom& G, const PacketState& st,
+                                                               const PotDesc& P, int mode, double h,
+                                                               double* acc) {
+  const int D = G.D;
+  if (mode & EPI_SCALE) {
+    const T s = (T)st.scale;
+    x.x *= s;
+    x.y *= s;
+  }
+  const double w = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+  if (mode & (EPI_REDP | EPI_REDQ)) {
+    acc[0] += w;
+    for (int l = 0; l < D; ++l) acc[1 + l] += w * (double)(j[l] - G.ax[l].n / 2);
+    if (mode & EPI_EKIN) {
+      double e = 0.0;
+      for (int l = 0; l < D; ++l) {
+        const double p = st.p_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dp;
+        e += 0.5 * G.ax[l].minv * p * p;
+      }
+      acc[D + 1] += w * e;
+    }
+    if (mode & EPI_REDQ) {
+      double q[MGK_MAXD];
+      for (int l = 0; l < D; ++l) q[l] = st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq;
+      acc[D + 1] += w * pot_eval(P, D, q, nullptr);
+    }
+  }
+  if (mode & EPI_V) {
+    double q[MGK_MAXD], g[MGK_MAXD];
+    for (int l = 0; l < D; ++l) q[l] = st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq;
+    const double V = pot_eval(P, D, q, g);
+    acc[0] += w;
+    for (int l = 0; l < D; ++l) acc[1 + l] += w * g[l];
+    x = cmul(x, phase_of<T>(h * V / G.hbar));
+  }
+  return x;
+}
+
+}  // namespace mgk

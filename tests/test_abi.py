@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every entry point that include/mgso.h
+declares; argument validation that happens before any device work.  CPU only:
+no compute call reaches a GPU here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgso.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(mg_[a-z0-9_]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1909_06412_amd import _lib
+    return _lib.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("mg_create", "mg_set_gaussian", "mg_set_potential", "mg_set_scheme", "mg_step",
+                 "mg_observables", "mg_adjoint", "mg_batch_step"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1909_06412_amd import _lib
+    assert sorted(_lib.exported_symbols()) == declared_functions()
+
+
+@pytest.mark.parametrize("D,N", [(0, []), (9, [4] * 9), (1, [7]), (1, [5]), (2, [8, 14]),
+                                 (1, [8192]), (1, [0])])
+def test_create_rejects_bad_shapes_without_touching_the_device(lib, D, N):
+    from paper_1909_06412_amd import _lib
+    h = ctypes.c_void_p()
+    Narr = np.asarray(N if N else [0], dtype=np.int32)
+    dq = np.ones(max(D, 1))
+    st = lib.mg_create(D, Narr.ctypes.data_as(_lib._ip), _lib.dptr(dq), _lib.dptr(dq), 1.0, 0,
+                       None, ctypes.byref(h))
+    assert st == _lib.MG_EINVAL
+    assert not h.value
+
+
+def test_create_rejects_bad_scalars(lib):
+    from paper_1909_06412_amd import _lib
+    h = ctypes.c_void_p()
+    N = np.asarray([8], dtype=np.int32)
+    for dq, hbar, prec in [(np.array([0.0]), 1.0, 0), (np.array([0.1]), 0.0, 0),
+                           (np.array([0.1]), 1.0, 7), (np.array([np.nan]), 1.0, 0)]:
+        st = lib.mg_create(1, N.ctypes.data_as(_lib._ip), _lib.dptr(dq), _lib.dptr(np.ones(1)),
+                           hbar, prec, None, ctypes.byref(h))
+        assert st == _lib.MG_EINVAL
+
+
+def test_null_context_calls_fail_cleanly(lib):
+    from paper_1909_06412_amd import _lib
+    assert lib.mg_step(None, 0.1, 1) == _lib.MG_EINVAL
+    assert lib.mg_observables(None, None) == _lib.MG_EINVAL
+    assert lib.mg_state_bytes(None) == 0
+    assert isinstance(lib.mg_last_error(None), bytes)

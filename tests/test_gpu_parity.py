@@ -1,0 +1,201 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on the
+same seeded inputs.  Tolerances: 1e-12 (relative l2 state error, and centres) for
+complex128 on short horizons; 1e-5 for complex64 (the error of the complex64 bulk
+is measured against the FP64 oracle, the reductions and centres stay FP64).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+TOL64 = 1e-5
+
+
+def _mg():
+    import paper_1909_06412_amd as mg
+    return mg
+
+
+def oracle_run(w, nsteps, dt=None):
+    g = O.Grid(w["N"], w["dq"], w["hbar"])
+    wp = O.gaussian(g, w["q0"], w["p0"], w["sigma"])
+    pot = O.potentials.from_spec(*w["potential"], w["D"])
+    gam = O.composition(w["comp"], w["order"])
+    O.run(wp, w["dt"] if dt is None else dt, nsteps, gam, pot, w["inv_mass"], w["split"])
+    return wp, pot
+
+
+def gpu_run(w, nsteps, precision=None, dt=None):
+    mg = _mg()
+    m = mg.from_workload(w, precision=precision)
+    m.step(w["dt"] if dt is None else dt, nsteps)
+    return m
+
+
+def rel_err(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def compare(w, nsteps, precision, tol, tol_ctr=None):
+    wp, _ = oracle_run(w, nsteps)
+    m = gpu_run(w, nsteps, precision)
+    psi, q, p, t = m.get_state()
+    tol_ctr = tol if tol_ctr is None else tol_ctr
+    e = rel_err(psi, wp.physical())
+    print(f"[parity] {w['name']} {precision} steps={nsteps} state={e:.3e} "
+          f"dq={np.max(np.abs(q - wp.q_ctr)):.3e} dp={np.max(np.abs(p - wp.p_ctr)):.3e}", flush=True)
+    assert np.max(np.abs(q - wp.q_ctr)) < tol_ctr
+    assert np.max(np.abs(p - wp.p_ctr)) < tol_ctr
+    assert e < tol
+    m.close()
+    return e
+
+
+def test_harmonic_1d_config_full_run_c128():
+    """64 points (one tile), 1000 Strang steps."""
+    w = W.harmonic_1d()
+    compare(w, w["steps"], "c128", 5e-12)
+
+
+def test_harmonic_3d_32cubed_multi_tile_c128():
+    w = W.harmonic_3d(seed=0, order=4, dt=0.05)
+    compare(w, 10, "c128", TOL128)
+
+
+@pytest.mark.parametrize("order,comp", [(6, "triple_jump"), (10, "triple_jump"), (6, "suzuki")])
+def test_harmonic_3d_high_orders_c128(order, comp):
+    w = W.harmonic_3d(seed=3, order=order, dt=0.1)
+    w["comp"] = comp
+    compare(w, 2, "c128", TOL128)
+
+
+def test_harmonic_3d_c64():
+    w = W.harmonic_3d(seed=1, order=4, dt=0.05, precision="c64")
+    compare(w, 10, "c64", TOL64, tol_ctr=1e-6)
+
+
+@pytest.mark.parametrize("shape", [(6, 10, 12), (90, 72), (24, 20, 18), (2, 4, 2), (180,),
+                                   (4, 6, 4, 10)])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_ragged_shapes_henon_heiles(shape, precision):
+    """Non-power-of-two lengths (radix 3 and 5 passes), ragged tiles, several sweeps."""
+    D = len(shape)
+    w = W.henon_heiles_8d(n=4, D=D, dq=0.6, lam=0.08)
+    w["N"] = list(shape)
+    w["dq"] = [min(0.6, 9.0 / n) for n in shape]
+    w["dt"] = 0.02
+    w["q0"] = [0.3] * D
+    w["p0"] = [0.2] * D
+    compare(w, 3, precision, TOL128 if precision == "c128" else TOL64,
+            tol_ctr=1e-12 if precision == "c128" else 1e-6)
+
+
+@pytest.mark.parametrize("split", ["TVT", "VTV"])
+def test_morse_repulsion_128x96(split):
+    w = W.morse_repulsion_2d(128, 96, steps=0, precision="c128")
+    w["split"] = split
+    compare(w, 40, "c128", TOL128)
+
+
+def test_henon_heiles_8d_small_grid():
+    w = W.henon_heiles_8d(n=4, D=8, dq=1.2)
+    compare(w, 2, "c128", TOL128)
+
+
+def test_quadratic_duschinsky():
+    w = W.duschinsky_3d(n=32, dq=0.4375)
+    w["steps"] = 4
+    w["dt"] = 0.05
+    w["comp"], w["order"] = "suzuki", 4
+    compare(w, 4, "c128", TOL128)
+
+
+def test_observables_match_oracle():
+    w = W.morse_repulsion_2d(64, 80, steps=0, precision="c128")
+    wp, pot = oracle_run(w, 25)
+    ob = O.observables(wp, pot, w["inv_mass"])
+    m = gpu_run(w, 25)
+    gb = m.observables()
+    for key in ("norm", "Ekin", "Epot", "E"):
+        assert abs(gb[key] - ob[key]) < 1e-12 * max(1.0, abs(ob[key])), key
+    for key in ("q", "p", "q_ctr", "p_ctr"):
+        np.testing.assert_allclose(gb[key], ob[key], rtol=0, atol=1e-12)
+    assert abs(gb["t"] - 25 * w["dt"]) < 1e-12
+
+
+def test_regrid_matches_oracle():
+    w = W.harmonic_3d(seed=2, order=2, dt=0.05)
+    wp, _ = oracle_run(w, 3)
+    new = wp.q_ctr + np.array([0.37, -0.21, 0.05])
+    ref = O.regrid(wp, new)
+    m = gpu_run(w, 3)
+    m.regrid(new)
+    psi, q, p, _ = m.get_state()
+    np.testing.assert_allclose(q, new, atol=0)
+    assert rel_err(psi, ref.physical()) < TOL128
+
+
+def test_set_state_random_then_substeps():
+    """Arbitrary (random) state through the set/get round trip and a few steps."""
+    mg = _mg()
+    N = [12, 20, 10]
+    g = O.Grid(N, [0.5, 0.4, 0.6])
+    psi0 = W.random_state(N, seed=7)
+    qc, pc = np.array([0.2, -0.1, 0.3]), np.array([0.5, 0.0, -0.4])
+    m = mg.MovingGrid(N, g.dq, [1.0, 0.7, 1.3], 1.0, "c128")
+    m.set_potential("henon_heiles", {"kappa": 1.0, "lam": 0.1})
+    m.set_scheme("TVT", "suzuki", 4)
+    m.set_state(psi0, qc, pc)
+    back, q, p, t = m.get_state()
+    assert np.array_equal(back, psi0) or rel_err(back, psi0) < 1e-15
+    m.step(0.03, 2)
+    wp = O.from_physical(g, psi0, qc, pc)
+    O.run(wp, 0.03, 2, O.composition("suzuki", 4), O.potentials.HenonHeiles(3, 1.0, 0.1),
+          [1.0, 0.7, 1.3])
+    psi, q, p, t = m.get_state()
+    assert rel_err(psi, wp.physical()) < TOL128
+    np.testing.assert_allclose(q, wp.q_ctr, atol=1e-12)
+
+
+def test_time_reversibility_on_gpu():
+    w = W.morse_repulsion_2d(64, 64, steps=0, precision="c128")
+    m = _mg().from_workload(w)
+    psi0, q0, p0, _ = m.get_state()
+    m.step(2.0, 30)
+    m.step(-2.0, 30)
+    psi, q, p, _ = m.get_state()
+    assert rel_err(psi, psi0) < 1e-11
+    np.testing.assert_allclose(q, q0, atol=1e-12)
+
+
+def test_unstable_step_reports_error():
+    """Strang with omega dt > 2 (Eq. (57)): the centres diverge and the step reports it."""
+    mg = _mg()
+    w = W.harmonic_1d()
+    w["potential"] = ("harmonic", {"k": [2.25], "s": [0.0]})
+    m = mg.from_workload(w)
+    with pytest.raises(mg.MgError) as ei:
+        m.step(1.5, 200)
+    assert ei.value.status == mg.MG_EUNSTABLE
+    with pytest.raises(mg.MgError) as ei:
+        m.step(0.01, 1)                     # state invalid until the next set_*
+    assert ei.value.status == mg.MG_ESTATE
+
+
+def test_nan_state_reports_unstable():
+    mg = _mg()
+    m = mg.MovingGrid([16], [0.5], [1.0])
+    m.set_potential("harmonic", {"k": [1.0], "s": [0.0]})
+    m.set_scheme()
+    psi = np.zeros(16, complex)
+    psi[3] = np.nan
+    m.set_state(psi, [0.0], [0.0])
+    with pytest.raises(mg.MgError) as ei:
+        m.step(0.1, 1)
+    assert ei.value.status == mg.MG_EUNSTABLE
