@@ -16,6 +16,7 @@
 
 #include "mgso.h"
 #include "mgso_sweep.h"
+#include "mgso_sweep16.h"
 
 using namespace mgk;
 
@@ -107,6 +108,8 @@ template <typename T> struct FinArgs {
   double forced[MGK_MAXD];
   typename CT<T>::type* A;
   typename CT<T>::type* M;
+  typename CT<T>::type* AG;   // group-combined tables (16-point path), may be null
+  typename CT<T>::type* MG;
 };
 
 template <typename T>
@@ -186,6 +189,37 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
         sincos(phi, &s, &c);
         const double sg = (j & 1) ? -inv_sqrt : inv_sqrt;
         a.A[ax.tab_off + j] = C{(decltype(C().x))(sg * c), (decltype(C().x))(-sg * s)};
+      }
+    }
+  }
+  // Group-combined tables of the 16-point path: one FP64 angle sum per entry.
+  if (G.fast16 && a.AG) {
+    const bool doA = a.mode == FIN_V || a.mode == FIN_BUILD_A;
+    const bool doM = a.mode == FIN_T || a.mode == FIN_REGRID;
+    if (doA || doM) {
+      const double h = a.mode == FIN_T ? a.h : 0.0;
+      for (int si = 0; si < G.nsweeps; ++si) {
+        const SweepDesc& sw = G.sw[si];
+        const int K = sw.b - sw.a;
+        const double mag = doA ? ldexp(1.0, -2 * K) : 1.0;   // prod 1/sqrt(16)
+        for (uint32_t g = threadIdx.x; g < sw.LG; g += NTHR) {
+          double ang = 0.0;
+          for (int l = sw.b - 1, sh = 0; l >= sw.a; --l, sh += 4) {
+            const int j = (int)((g >> sh) & 15u);
+            const AxisDesc& ax = G.ax[l];
+            if (doA) {
+              ang += M_PI * (double)(j & 1) - st.p_c[l] * (double)j * ax.dq / hbar;
+            } else {
+              const double p = st.p_c[l] + (double)(j - 8) * ax.dp;
+              ang -= (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / hbar;
+            }
+          }
+          double s, c;
+          sincos(ang, &s, &c);
+          C v = C{(decltype(C().x))(mag * c), (decltype(C().x))(mag * s)};
+          if (doA) a.AG[sw.gtab_off + g] = v;
+          else a.MG[sw.gtab_off + g] = v;
+        }
       }
     }
   }
@@ -465,6 +499,9 @@ struct mg_ctx {
   void* d_tw = nullptr;
   void* d_A = nullptr;
   void* d_M = nullptr;
+  void* d_AG = nullptr;
+  void* d_MG = nullptr;
+  S16Desc s16[MGK_MAXD];
   double* d_part = nullptr;
   void* psi = nullptr;
   bool psi_owned = false;
@@ -529,15 +566,78 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
     for (int l = 0; l < c->D; ++l) a.forced[l] = forced[l];
   a.A = (C*)c->d_A;
   a.M = (C*)c->d_M;
+  a.AG = (C*)c->d_AG;
+  a.MG = (C*)c->d_MG;
   hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(NTHR), 0, c->stream, a);
   HIPCHK(c, hipGetLastError());
   return MG_OK;
 }
 
-// Launch sweep si; returns the number of blocks (for the finalize).
-template <typename T>
-static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk) {
+template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, const S16Args<T>& a, int grid) {
   typedef typename CT<T>::type C;
+  const size_t lds = K > 1 ? (size_t)4352 * sizeof(C) : (size_t)(256 / 64) * MGK_NACC * sizeof(double);
+  if constexpr (EPI == EPI_V) {
+    switch (c->pot.kind) {
+      case MG_POT_FREE: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 0>), dim3(grid), dim3(256), lds, c->stream, a); break;
+      case MG_POT_HARMONIC: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 1>), dim3(grid), dim3(256), lds, c->stream, a); break;
+      case MG_POT_HENON_HEILES: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 3>), dim3(grid), dim3(256), lds, c->stream, a); break;
+      default: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 4>), dim3(grid), dim3(256), lds, c->stream, a); break;
+    }
+  } else {
+    hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI>), dim3(grid), dim3(256), lds, c->stream, a);
+  }
+}
+
+template <typename T, bool INV, int EPI> static void launch16_k(mg_ctx* c, const S16Args<T>& a, int grid) {
+  switch (a.d.K) {
+    case 1: launch16<T, 1, INV, EPI>(c, a, grid); break;
+    case 2: launch16<T, 2, INV, EPI>(c, a, grid); break;
+    default: launch16<T, 3, INV, EPI>(c, a, grid); break;
+  }
+}
+
+// Launch sweep si; returns the number of blocks (for the finalize).  fast = use
+// the 16-point kernel when the packet qualifies (only plain, REDP and V epilogues).
+template <typename T>
+static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk,
+                              bool fast = false) {
+  typedef typename CT<T>::type C;
+  if (fast && c->geom.fast16 && pot_is_cubic(c->pot.kind) && (epi == 0 || epi == EPI_REDP || epi == EPI_V)) {
+    S16Args<T> a;
+    a.geom = c->d_geom;
+    a.st = c->d_st;
+    a.pot = c->d_pot;
+    a.src = (const C*)src;
+    a.dst = (C*)dst;
+    a.AG = (const C*)c->d_AG;
+    a.MG = (const C*)c->d_MG;
+    a.partials = c->d_part;
+    a.d = c->s16[si];
+    a.h = h;
+    const int grid = grid_for(a.d.ntiles);
+    *nblk = grid;
+    ProfEntry pe{};
+    if (c->opt_profile) {
+      HIPCHK(c, hipEventCreate(&pe.e0));
+      HIPCHK(c, hipEventCreate(&pe.e1));
+      HIPCHK(c, hipEventRecord(pe.e0, c->stream));
+    }
+    const bool inv = dir == DIR_INV;
+    if (!inv) {
+      if (epi == EPI_REDP) launch16_k<T, false, EPI_REDP>(c, a, grid);
+      else launch16_k<T, false, 0>(c, a, grid);
+    } else {
+      if (epi == EPI_V) launch16_k<T, true, EPI_V>(c, a, grid);
+      else launch16_k<T, true, 0>(c, a, grid);
+    }
+    HIPCHK(c, hipGetLastError());
+    if (c->opt_profile) {
+      HIPCHK(c, hipEventRecord(pe.e1, c->stream));
+      pe.cls = si * 64 + dir * 32 + epi;
+      c->prof_pending.push_back(pe);
+    }
+    return MG_OK;
+  }
   SweepArgs<T> a;
   a.geom = c->d_geom;
   a.st = c->d_st;
@@ -589,11 +689,13 @@ template <typename T> static mg_status launch_pointwise(mg_ctx* c, int epi, doub
 // Forward transform of src into dst (dst may equal src); the last sweep reduces
 // the momentum moments with epilogue `epi_last`.
 template <typename T>
-static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last) {
+static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last,
+                                   bool fast = false) {
   const int ns = c->geom.nsweeps;
   for (int s = 0; s < ns; ++s) {
     int nb;
-    mg_status r = launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb);
+    mg_status r =
+        launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb, fast);
     if (r) return r;
     if (s == ns - 1) *nblk_last = nb;
   }
@@ -601,11 +703,12 @@ static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int ep
 }
 
 template <typename T>
-static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last) {
+static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last,
+                                   bool fast = false) {
   const int ns = c->geom.nsweeps;
   for (int s = ns - 1; s >= 0; --s) {
     int nb;
-    mg_status r = launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb);
+    mg_status r = launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb, fast);
     if (r) return r;
     if (s == 0) *nblk_last = nb;
   }
@@ -616,9 +719,9 @@ template <typename T> static mg_status run_unit(mg_ctx* c, const Unit& u) {
   mg_status r;
   int nb = 0;
   if (u.hasT) {
-    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb))) return r;
+    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb, true))) return r;
     if ((r = launch_finalize<T>(c, FIN_T, u.hT, nb, nullptr))) return r;
-    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb))) return r;
+    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb, true))) return r;
     if (u.hasV && (r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
   } else if (u.hasV) {
     if ((r = launch_pointwise<T>(c, EPI_V, u.hV, &nb))) return r;
@@ -700,6 +803,61 @@ static mg_status upload_state_scalars(mg_ctx* c, const double* q, const double* 
   return MG_OK;
 }
 
+template <int K> static hipError_t set_lds_attr_v(int bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 0>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  return e;
+}
+
+static int ilog2u(uint64_t v) {
+  int l = 0;
+  while ((1ull << l) < v) ++l;
+  return (1ull << l) == v ? l : -1;
+}
+
+// The 16-point sweep kernels apply when every axis has 16 points and D >= 3; the
+// sweep plan then consists of 4096-point tiles with power-of-two runs.
+static void setup_fast16(mg_ctx* c) {
+  PacketGeom& G = c->geom;
+  G.fast16 = 0;
+  G.gtab_len = 0;
+  if (G.D < 3) return;
+  for (int l = 0; l < G.D; ++l)
+    if (G.ax[l].n != 16) return;
+  int off = 0;
+  for (int si = 0; si < G.nsweeps; ++si) {
+    SweepDesc& sw = G.sw[si];
+    S16Desc& d = c->s16[si];
+    memset(&d, 0, sizeof(d));
+    d.K = sw.b - sw.a;
+    d.a = sw.a;
+    d.kind = sw.kind;
+    if (sw.T != 4096 || d.K < 1 || d.K > 3) return;
+    if (sw.kind == 0 && (sw.ob != 1 || sw.LG != 4096)) return;
+    if (sw.kind != (d.K == 3 ? 0 : 1)) return;  // the kernels fix the tile kind by K
+    d.lr = ilog2u(sw.kind == 0 ? 1 : sw.r);
+    d.lI = ilog2u(sw.I);
+    d.lLG = ilog2u(sw.LG);
+    d.ltiles_i = ilog2u(sw.tiles_i);
+    if (d.lr < 0 || d.lI < 0 || d.lLG < 0 || d.ltiles_i < 0) return;
+    if (sw.kind == 1 && sw.I % sw.r) return;
+    for (int e = 0; e < d.K; ++e) d.lS[e] = 4 * (d.K - 1 - e) + d.lr;
+    d.tiles_i = sw.tiles_i;
+    d.ntiles = sw.ntiles;
+    d.gtab_off = off;
+    sw.gtab_off = off;
+    off += (int)sw.LG;
+  }
+  G.gtab_len = off;
+  G.fast16 = 1;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -724,6 +882,7 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
     return MG_EINVAL;
   }
   c->geom.off = 0;
+  setup_fast16(c);
   c->pot.kind = MG_POT_FREE;
   c->pot.D = D;
   hipError_t e = hipSuccess;
@@ -735,6 +894,20 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   if (e == hipSuccess) e = hipMalloc(&c->d_A, (size_t)c->geom.tab_len * c->csize);
   if (e == hipSuccess) e = hipMalloc(&c->d_M, (size_t)c->geom.tab_len * c->csize);
   if (e == hipSuccess) e = hipMalloc(&c->d_part, (size_t)MAX_BLOCKS * MGK_NACC * sizeof(double));
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, (size_t)c->geom.gtab_len * c->csize);
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, (size_t)c->geom.gtab_len * c->csize);
+  if (e == hipSuccess && c->geom.fast16 && prec == MG_C128) {
+    where = "hipFuncSetAttribute";
+    const int bytes = 4352 * (int)sizeof(double2);
+    e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, false, EPI_REDP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, false, EPI_REDP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess) e = set_lds_attr_v<2>(bytes);
+    if (e == hipSuccess) e = set_lds_attr_v<3>(bytes);
+  }
   if (e == hipSuccess) where = "hipMemcpy";
   if (e == hipSuccess) e = hipMemcpy(c->d_geom, &c->geom, sizeof(PacketGeom), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(c->d_pot, &c->pot, sizeof(PotDesc), hipMemcpyHostToDevice);
@@ -776,6 +949,8 @@ void mg_destroy(mg_ctx* c) {
   hipFree(c->d_A);
   hipFree(c->d_M);
   hipFree(c->d_part);
+  if (c->d_AG) hipFree(c->d_AG);
+  if (c->d_MG) hipFree(c->d_MG);
   delete c;
 }
 

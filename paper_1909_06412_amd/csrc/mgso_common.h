@@ -95,6 +95,8 @@ struct SweepDesc {
   DivW dtiles_i;          // tile -> (o, inner block)
   uint32_t S[MGK_MAXD];   // LDS stride of each axis of the group (index l - a)
   Div32 dS[MGK_MAXD];
+  int32_t gtab_off;       // offset of the group-combined phase tables (16-point path)
+  int32_t pad;
 };
 
 struct PacketGeom {
@@ -103,6 +105,8 @@ struct PacketGeom {
   uint64_t N_total;       // points (<= 2^32; 16^8 = 2^32 needs 64 bits)
   uint64_t off;           // element offset of this packet in the state buffer
   int32_t tab_len;        // sum_l N_l (A and M tables)
+  int32_t fast16;         // every axis has 16 points and D >= 3: 16-point sweep kernels
+  int32_t gtab_len;       // sum over sweeps of the group sizes (combined tables)
   int32_t pad1;
   double hbar;
   AxisDesc ax[MGK_MAXD];

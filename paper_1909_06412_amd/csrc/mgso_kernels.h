@@ -216,9 +216,12 @@ __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_
 // ---------------------------------------------------------------------------
 // Potentials (FP64): value and gradient at one grid point.
 // ---------------------------------------------------------------------------
+// PK >= 0 fixes the kind at compile time (specialised kernels); PK < 0 dispatches
+// on P.kind at run time.
+template <int PK = -1>
 __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double* q, double* g) {
   double V = 0.0;
-  switch (P.kind) {
+  switch (PK >= 0 ? PK : P.kind) {
     case 1: {  // harmonic: k[D], s[D]
       for (int l = 0; l < D; ++l) {
         const double x = q[l] - P.p[D + l];
@@ -273,6 +276,58 @@ __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double
       break;
   }
   return V;
+}
+
+// exp(-i phi) for the complex64 path without branches: quadrant reduction in FP64
+// (n = rint(2 phi / pi), r = phi - n pi/2 with pi/2 split in two parts so that the
+// reduction error stays near 1e-16 for |phi| < 1e6), then the Taylor series of
+// sin and cos to x^9 / x^8 in FP32 (truncation below 3e-9 on |r| <= pi/4), then
+// rotation by the quadrant.
+__device__ __forceinline__ float2 phase_poly(double phi) {
+  const double two_over_pi = 0.63661977236758134307553505349006;
+  // pi/2 split so that n * pio2_hi is exact (32-bit mantissa) (Cody-Waite)
+  const double pio2_hi = 1.5707963267341256;
+  const double pio2_lo = 6.077100506506192e-11;
+  const double n = rint(phi * two_over_pi);
+  const float r = (float)((phi - n * pio2_hi) - n * pio2_lo);
+  const float r2 = r * r;
+  const float sn = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
+  const float cs = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320))));
+  const int q = (int)n & 3;
+  // exp(i phi) = exp(i q pi/2) (cs + i sn)
+  float c, s;
+  if (q == 0) { c = cs; s = sn; }
+  else if (q == 1) { c = -sn; s = cs; }
+  else if (q == 2) { c = -cs; s = -sn; }
+  else { c = sn; s = -cs; }
+  return float2{c, -s};
+}
+
+// The same in FP64 for the complex128 path: Taylor series to x^17 / x^16 on
+// |r| <= pi/4 (truncation below 1e-19).
+__device__ __forceinline__ double2 phase_poly64(double phi) {
+  const double two_over_pi = 0.63661977236758134307553505349006;
+  const double pio2_hi = 1.5707963267341256;   // as in phase_poly
+  const double pio2_lo = 6.077100506506192e-11;
+  const double n = rint(phi * two_over_pi);
+  const double r = (phi - n * pio2_hi) - n * pio2_lo;
+  const double r2 = r * r;
+  // sin r = r - r^3 P(r^2), P = 1/3! - r^2/5! + ... - r^14/17!  (Horner from the top)
+  const double ps =
+      ((((((((-1.0 / 355687428096000.0) * r2 + 1.0 / 1307674368000.0) * r2 - 1.0 / 6227020800.0) * r2 +
+           1.0 / 39916800.0) * r2 - 1.0 / 362880.0) * r2 + 1.0 / 5040.0) * r2 - 1.0 / 120.0) * r2 + 1.0 / 6.0);
+  const double sn = r - r * r2 * ps;              // r - r^3/6 + r^5/120 - ...
+  // cos r = 1 + r^2 Q(r^2), Q = -1/2! + r^2/4! - ... + r^14/16!
+  const double pc = ((((((((1.0 / 20922789888000.0) * r2 - 1.0 / 87178291200.0) * r2 + 1.0 / 479001600.0) * r2 -
+                   1.0 / 3628800.0) * r2 + 1.0 / 40320.0) * r2 - 1.0 / 720.0) * r2 + 1.0 / 24.0) * r2 - 0.5);
+  const double cs = 1.0 + r2 * pc;
+  const int q = (int)n & 3;
+  double c, s;
+  if (q == 0) { c = cs; s = sn; }
+  else if (q == 1) { c = -sn; s = cs; }
+  else if (q == 2) { c = -cs; s = -sn; }
+  else { c = sn; s = -cs; }
+  return double2{c, -s};
 }
 
 // exp(-i phi) with phi in FP64, rounded to the storage precision.

@@ -1,0 +1,358 @@
+// mgso_sweep16.h -- sweep kernel for packets whose axes all have 16 points
+// (the 8-D Henon-Heiles grid 16^8 and any 16^D, D >= 3).
+//
+// A tile holds 4096 points: the K group axes of the sweep (16^K points) times a
+// run of r = 4096 / 16^K consecutive inner indices (r = 1 when the group contains
+// the innermost axis).  256 threads; for every group axis there are exactly 256
+// lines of 16 points, one per thread, transformed by a radix-16 DFT in registers.
+// Axes are taken outermost first: the first one is loaded straight from HBM into
+// registers (lanes run along its large stride, so a wave reads whole 128-byte
+// lines); the others go through LDS; the last one is stored straight from
+// registers when its stride is >= 16 points, else through one more LDS transpose
+// so that a wave writes 512 contiguous bytes.
+//
+// The per-axis phase factors of the kinetic substep (Sec. II.G.2, Eq. (55)) are
+// applied once per point from tables combined over the sweep's group axes:
+//   AG[g] = prod_{l in group} A_l(j_l)   (forward: on load; inverse: conj on store)
+//   MG[g] = prod_{l in group} M_l(k_l)   (inverse: on load)
+// built in FP64 (one sincos of the summed angle) and rounded once.
+#pragma once
+#include "mgso_kernels.h"
+
+namespace mgk {
+
+struct S16Desc {
+  int32_t K;          // group axes (1..3)
+  int32_t a;          // first group axis
+  int32_t kind;       // 0: tile = 16^K contiguous points (r = 1), 1: 16^K x r
+  int32_t lr;         // log2 r
+  int32_t lI;         // log2 I (inner extent)
+  int32_t lLG;        // log2 16^K
+  int32_t lS[3];      // log2 of the tile stride of group axis e (e = 0 outermost)
+  uint32_t tiles_i;   // tiles along the inner extent (kind 1)
+  int32_t ltiles_i;   // log2 tiles_i
+  uint32_t ntiles;
+  int32_t gtab_off;   // offset of this sweep's AG / MG tables
+};
+
+template <typename T> struct S16Args {
+  const PacketGeom* geom;
+  const PacketState* st;
+  const PotDesc* pot;
+  const typename CT<T>::type* src;
+  typename CT<T>::type* dst;
+  const typename CT<T>::type* AG;
+  const typename CT<T>::type* MG;
+  double* partials;
+  S16Desc d;
+  double h;
+};
+
+// 16-point DFT in registers, natural order in and out (4 x 4 decomposition).
+template <typename T, bool INV, typename C> __device__ __forceinline__ void dft16(C* x) {
+  const T c1 = (T)0.92387953251128675612818318939679;  // cos(pi/8)
+  const T s1 = (T)0.38268343236508977172845998403040;  // sin(pi/8)
+  const T r2 = (T)0.70710678118654752440084436210485;
+  C y[16];
+  // DFT4 over n1 for each n2: inputs x[4 n1 + n2]
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    C v[4] = {x[n2], x[4 + n2], x[8 + n2], x[12 + n2]};
+    dft4(v, INV);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) y[4 * n2 + k1] = v[k1];
+  }
+  // twiddles W16^(n2 k1), W16 = exp(-+ 2 pi i / 16)
+  auto tw = [&](C v, int m) -> C {
+    // exp(-i pi m / 8) for forward, conjugate for inverse
+    T c, s;
+    switch (m) {
+      case 1: c = c1; s = s1; break;
+      case 2: c = r2; s = r2; break;
+      case 3: c = s1; s = c1; break;
+      case 6: c = -r2; s = r2; break;
+      default: c = -c1; s = -s1; break;  // m = 9: cos(9pi/8) = -c1, sin(9pi/8) = -s1
+    }
+    if (!INV) s = -s;
+    return C{v.x * c - v.y * s, v.x * s + v.y * c};
+  };
+  y[4 * 1 + 1] = tw(y[5], 1);
+  y[4 * 1 + 2] = tw(y[6], 2);
+  y[4 * 1 + 3] = tw(y[7], 3);
+  y[4 * 2 + 1] = tw(y[9], 2);
+  y[4 * 2 + 2] = rot(y[10], INV);  // W^4 = -+ i
+  y[4 * 2 + 3] = tw(y[11], 6);
+  y[4 * 3 + 1] = tw(y[13], 3);
+  y[4 * 3 + 2] = tw(y[14], 6);
+  y[4 * 3 + 3] = tw(y[15], 9);
+  // DFT4 over n2 for each k1: X[k1 + 4 k2]
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C v[4] = {y[k1], y[4 + k1], y[8 + k1], y[12 + k1]};
+    dft4(v, INV);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = v[k2];
+  }
+}
+
+__device__ __forceinline__ uint32_t pad16(uint32_t t) { return t + (t >> 4); }
+
+// Lagrange weight of node i (nodes at line points 0, 5, 10, 15) at line point k:
+// a cubic through the four nodes reproduces any polynomial of degree <= 3.
+__host__ __device__ constexpr double lag4(int k, int i) {
+  const int nd[4] = {0, 5, 10, 15};
+  double num = 1.0, den = 1.0;
+  for (int j = 0; j < 4; ++j)
+    if (j != i) {
+      num *= (double)(k - nd[j]);
+      den *= (double)(nd[i] - nd[j]);
+    }
+  return num / den;
+}
+
+// Potentials that are polynomials of degree <= 3 in each coordinate (free,
+// harmonic, quadratic, Henon-Heiles): along a line of 16 points V and dV/dq are
+// cubics of the line coordinate, so four exact evaluations determine all 16.
+// (These are the only kinds a 16^D grid with D >= 3 can carry.)
+static inline bool pot_is_cubic(int kind) { return kind != 2; }
+
+template <typename T> __device__ __forceinline__ typename CT<T>::type phase_t(double phi);
+template <> __device__ __forceinline__ float2 phase_t<float>(double phi) { return phase_poly(phi); }
+template <> __device__ __forceinline__ double2 phase_t<double>(double phi) { return phase_poly64(phi); }
+
+// Potential part of the line epilogue: evaluate V and dV/dq at line points
+// 0, 5, 10, 15 (coordinates from the fixed indices jfix and the line axis L),
+// accumulate sum_k w_k dV/dq(q_k) = sum_i u_i dV/dq(node i) into acc[1..D] and
+// return the node values Vn for the interpolation of V along the line.
+template <int PK>
+__device__ __forceinline__ void line_potential(int L, const int* jfix, const double* u, double* Vn,
+                                               const PacketGeom& G, const PacketState& st, const PotDesc& P,
+                                               double* acc) {
+  const int D = G.D;
+  double q[MGK_MAXD], gr[MGK_MAXD];
+#pragma unroll
+  for (int l = 0; l < MGK_MAXD; ++l)
+    if (l < D) q[l] = st.q_c[l] + (double)(jfix[l] - 8) * G.ax[l].dq;
+  const double qL0 = st.q_c[L] - 8.0 * G.ax[L].dq, dqL = G.ax[L].dq;
+#pragma unroll 1
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l)
+      if (l == L) q[l] = qL0 + (double)(5 * i) * dqL;
+    const double Vi = pot_eval<PK>(P, D, q, gr);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j == i) Vn[j] = Vi;
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l)
+      if (l < D) acc[1 + l] += u[i] * gr[l];
+  }
+}
+
+// Epilogue on a line held in registers (strided tiles): moments (REDP) or the
+// potential substep (V) with weights w_k = |x_k|^2.
+template <typename T, int EPI, int PK>
+__device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, uint64_t f, const PacketGeom& G,
+                                              const PacketState& st, const PotDesc& P, double hh, double* acc) {
+  const int D = G.D;
+  int jfix[MGK_MAXD];
+#pragma unroll
+  for (int l = 0; l < MGK_MAXD; ++l)
+    if (l < D) jfix[l] = (int)((f >> (4 * (D - 1 - l))) & 15);
+  double wl = 0.0, ml = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const double w = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
+    wl += w;
+    if (EPI == EPI_REDP) ml += w * (double)(k - 8);
+    if (EPI == EPI_V) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) u[i] += lag4(k, i) * w;
+    }
+  }
+  acc[0] += wl;
+  if (EPI == EPI_REDP) {
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l)
+      if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
+  }
+  if (EPI == EPI_V) {
+    double Vn[4];
+    line_potential<PK>(L, jfix, u, Vn, G, st, P, acc);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const double V = lag4(k, 0) * Vn[0] + lag4(k, 1) * Vn[1] + lag4(k, 2) * Vn[2] + lag4(k, 3) * Vn[3];
+      x[k] = cmul(x[k], phase_t<T>(hh * V));
+    }
+  }
+}
+
+template <typename T, int K, bool INV, int EPI, int PK = -1>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void k_sweep16(S16Args<T> a) {
+  typedef typename CT<T>::type C;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  C* lds = reinterpret_cast<C*>(lds_raw);
+  const PacketGeom& G = *a.geom;
+  const S16Desc d = a.d;
+  // every 16^D plan has contiguous 16^3 tiles for K = 3 and strided tiles below
+  constexpr int KIND = K == 3 ? 0 : 1;
+  const int D = G.D;
+  const uint32_t t = threadIdx.x;
+  double acc[MGK_NACC];
+#pragma unroll
+  for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
+  const double hh = a.h / G.hbar;
+  const uint64_t off = G.off;  // read once: stores to dst must not force reloads
+  const C* __restrict__ src = a.src + off;
+  C* __restrict__ dst = a.dst + off;
+  const C* __restrict__ AG = a.AG + d.gtab_off;
+  const C* __restrict__ MG = a.MG + d.gtab_off;
+
+  for (uint32_t tile = blockIdx.x; tile < d.ntiles; tile += gridDim.x) {
+    uint64_t flat0;
+    if (KIND == 0) {
+      flat0 = (uint64_t)tile << 12;
+    } else {
+      const uint32_t o = tile >> d.ltiles_i;
+      const uint32_t ib = tile & (d.tiles_i - 1);
+      flat0 = ((uint64_t)o << (d.lLG + d.lI)) + ((uint64_t)ib << d.lr);
+    }
+    auto flat_of = [&](uint32_t tau) -> uint64_t {
+      if (KIND == 0) return flat0 + tau;
+      return flat0 + ((uint64_t)(tau >> d.lr) << d.lI) + (tau & ((1u << d.lr) - 1));
+    };
+    auto g_of = [&](uint32_t tau) -> uint32_t { return KIND == 0 ? tau : (tau >> d.lr); };
+    // Along a line of axis e the tile stride S >= r, so consecutive points are a
+    // uniform distance apart in memory and in the group tables.
+    auto mem_stride = [&](uint32_t S_) -> uint64_t {
+      return KIND == 0 ? (uint64_t)S_ : ((uint64_t)(S_ >> d.lr) << d.lI);
+    };
+    auto tab_stride = [&](uint32_t S_) -> uint32_t { return KIND == 0 ? S_ : (S_ >> d.lr); };
+
+    C x[16];
+    // ---- first axis: the outermost group axis (largest tile stride), coalesced
+    int e = 0;
+    uint32_t S = 1u << d.lS[0];
+    uint32_t tau0 = ((t >> d.lS[0]) << (d.lS[0] + 4)) + (t & (S - 1));
+    {
+      // uniform (scalar) base per point k + a 32-bit per-lane offset: the loads
+      // use scalar-base addressing and stay in flight together
+      const C* __restrict__ pre = INV ? MG : AG;
+      const uint64_t ms = mem_stride(S);
+      const uint32_t ts = tab_stride(S);
+      const uint32_t lane = (uint32_t)(flat_of(tau0) - flat0);
+      const uint32_t glane = g_of(tau0);
+      const C* __restrict__ tsrc = src + flat0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const C* __restrict__ bk = tsrc + (uint64_t)k * ms;
+        x[k] = bk[lane];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], pre[k * ts + glane]);
+      dft16<T, INV>(x);
+    }
+    // ---- inner axes through LDS
+#pragma unroll
+    for (int ee = 1; ee < K; ++ee) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
+      __syncthreads();
+      e = ee;
+      S = 1u << d.lS[e];
+      tau0 = ((t >> d.lS[e]) << (d.lS[e] + 4)) + (t & (S - 1));
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = lds[pad16(tau0 + k * S)];
+      __syncthreads();
+      if (ee < K - 1) dft16<T, INV>(x);
+    }
+    // inverse: fetch the conj(A) factors of the store now, so that their latency
+    // overlaps the last DFT and the epilogue
+    // (a contiguous tile fetches them after the epilogue instead, to keep the
+    // epilogue's registers free; they then overlap the LDS transpose)
+    C pv[KIND == 1 ? 16 : 1];
+    if (INV && KIND == 1) {
+      const uint32_t ts = tab_stride(S);
+      const uint32_t glane = g_of(tau0);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) pv[k] = AG[k * ts + glane];
+    }
+    if (K > 1) dft16<T, INV>(x);
+    if constexpr (KIND == 1) {
+      // ---- strided tile: epilogue on the thread's line (packet axis L), store
+      // 128-byte segments straight from registers
+      const int L = d.a + e;
+      if (EPI) line_epilogue<T, EPI, PK>(x, L, flat_of(tau0), G, *a.st, *a.pot, hh, acc);
+      const uint64_t ms = mem_stride(S);
+      const uint32_t lane = (uint32_t)(flat_of(tau0) - flat0);
+      C* __restrict__ tdst = dst + flat0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        C v = x[k];
+        if (INV) v = cmulc(v, pv[k]);
+        C* __restrict__ bk = tdst + (uint64_t)k * ms;
+        bk[lane] = v;
+      }
+    } else {
+      // ---- contiguous tile: the last axis is contiguous.  Transpose through LDS;
+      // thread t then owns positions t + 256 m, a line along the outermost group
+      // axis (packet axis a), and streams it: pass 1 reduces, pass 2 applies the
+      // phase and the conj(A) factor and stores 512 contiguous bytes per wave.
+#pragma unroll
+      for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
+      __syncthreads();
+      double Vn[4] = {0.0, 0.0, 0.0, 0.0};
+      if (EPI) {
+        const int L = d.a;
+        int jfix[MGK_MAXD];
+        const uint64_t f = flat0 + t;
+#pragma unroll
+        for (int l = 0; l < MGK_MAXD; ++l)
+          if (l < D) jfix[l] = (int)((f >> (4 * (D - 1 - l))) & 15);
+        double wl = 0.0, ml = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+          const C y = lds[pad16(t + 256 * m)];
+          const double w = (double)y.x * (double)y.x + (double)y.y * (double)y.y;
+          wl += w;
+          if (EPI == EPI_REDP) ml += w * (double)(m - 8);
+          if (EPI == EPI_V) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) u[i] += lag4(m, i) * w;
+          }
+        }
+        acc[0] += wl;
+        if (EPI == EPI_REDP) {
+#pragma unroll
+          for (int l = 0; l < MGK_MAXD; ++l)
+            if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
+        }
+        if (EPI == EPI_V) line_potential<PK>(L, jfix, u, Vn, G, *a.st, *a.pot, acc);
+      }
+      C* __restrict__ tdst = dst + flat0;
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        C v = lds[pad16(t + 256 * m)];
+        if (EPI == EPI_V) {
+          const double V = lag4(m, 0) * Vn[0] + lag4(m, 1) * Vn[1] + lag4(m, 2) * Vn[2] + lag4(m, 3) * Vn[3];
+          v = cmul(v, phase_t<T>(hh * V));
+        }
+        if (INV) v = cmulc(v, AG[t + 256 * m]);
+        tdst[256 * m + t] = v;
+      }
+      __syncthreads();
+    }
+  }
+  if (EPI) {
+    // the inverse tables carry 1/sqrt(16) per axis: the sums above miss 16^-K
+    if (INV) {
+      const double sc = ldexp(1.0, -4 * K);
+#pragma unroll
+      for (int k = 0; k < MGK_NACC; ++k) acc[k] *= sc;
+    }
+    block_reduce<256>(acc, D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
+  }
+}
+
+}  // namespace mgk

@@ -199,3 +199,16 @@ def test_nan_state_reports_unstable():
     with pytest.raises(mg.MgError) as ei:
         m.step(0.1, 1)
     assert ei.value.status == mg.MG_EUNSTABLE
+
+
+@pytest.mark.parametrize("D", [3, 4, 5, 6])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_sixteen_point_sweep_kernels(D, precision):
+    """Grids 16^D use the 16-point sweep kernels (radix-16 lines in registers,
+    group-combined phase tables); every tile shape of the 16^8 plan appears here."""
+    w = W.henon_heiles_8d(n=16, D=D, dq=0.625)
+    w["q0"] = [2.0 - 0.1 * l for l in range(D)]
+    w["p0"] = [0.1 * l for l in range(D)]
+    nsteps = 3 if D < 6 else 1
+    compare(w, nsteps, precision, TOL128 if precision == "c128" else TOL64,
+            tol_ctr=1e-12 if precision == "c128" else 1e-6)
