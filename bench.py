@@ -39,6 +39,8 @@ def workload(name):
         return W.morse_repulsion_2d()
     if name == "c4":
         return W.henon_heiles_8d()
+    if name == "c5":
+        return W.morse_batch()
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -51,12 +53,27 @@ def cpu_sample(name):
         return W.morse_repulsion_2d(precision="c128"), 200, "200 Strang steps of the 256^2 Morse model"
     if name == "c2":
         return W.harmonic_3d(seed=0, order=4, dt=0.01), 20, "20 Suzuki-4 steps of the 32^3 harmonic model"
+    if name == "c5":
+        return W.morse_batch(precision="c128")[:8], 20, "20 Strang steps of 8 of the 256 packets"
     return W.harmonic_1d(), 1000, "1000 Strang steps of the 64-point oscillator"
 
 
 def run_cpu_baseline(name):
     import oracle as O
     w, nsteps, desc = cpu_sample(name)
+    if isinstance(w, list):
+        t0 = time.perf_counter()
+        pts = 0
+        for wi in w:
+            g = O.Grid(wi["N"], wi["dq"], wi["hbar"])
+            wp = O.gaussian(g, wi["q0"], wi["p0"], wi["sigma"])
+            pot = O.potentials.from_spec(*wi["potential"], wi["D"])
+            O.run(wp, wi["dt"], nsteps, O.composition(wi["comp"], wi["order"]), pot, wi["inv_mass"],
+                  wi["split"])
+            pts += int(np.prod(wi["N"]))
+        dt = time.perf_counter() - t0
+        return {"value": pts * nsteps / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
+                "sample": f"{desc}, FP64 NumPy, {dt:.1f} s"}
     g = O.Grid(w["N"], w["dq"], w["hbar"])
     wp = O.gaussian(g, w["q0"], w["p0"], w["sigma"])
     pot = O.potentials.from_spec(*w["potential"], w["D"])
@@ -92,12 +109,57 @@ def timed_run(w, precision, steps, warmup, profile):
     return m, el, prof, obs
 
 
+def batch_run(ws, precision, steps, warmup):
+    import paper_1909_06412_amd as mg
+    import torch
+    b = mg.batch_from_workloads(ws, precision=precision)
+    log(f"batch of {b.B} packets, {b.points} points, {precision}; warmup {warmup}")
+    if warmup:
+        b.step(ws[0]["dt"], warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(ws[0]["dt"], steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    obs = b.observables()
+    log(f"batch {precision}: {steps} steps in {el:.3f} s; norms {min(o['norm'] for o in obs):.12f}"
+        f"..{max(o['norm'] for o in obs):.12f}")
+    pts = b.points
+    b.close()
+    return el, pts, obs
+
+
+def main_batch(args):
+    ws = W.morse_batch(precision="c64")
+    el, pts, obs = batch_run(ws, "c64", args.steps, args.warmup)
+    value = pts * args.steps / el
+    out = {
+        "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "morse_batch_256_packets", "packets": len(ws), "points": pts,
+                   "potential": "morse_repulsion", "composition": "strang", "order": 2, "split": "TVT",
+                   "dt": ws[0]["dt"], "precision": "c64", "launch": "one persistent kernel per call"},
+    }
+    if not args.no_fp64:
+        el2, _, obs2 = batch_run(W.morse_batch(precision="c128"), "c128", args.steps, args.warmup)
+        d = max(abs(a["norm"] - b_["norm"]) for a, b_ in zip(obs, obs2))
+        d = max(d, max(float(np.max(np.abs(a["q"] - b_["q"]))) for a, b_ in zip(obs, obs2)))
+        out["fp64"] = {"value": pts * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
+                       "c64_speedup": el2 / el, "c64_vs_fp64_observable_maxdiff": d}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = run_cpu_baseline("c5")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -109,6 +171,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
+    if args.workload == "c5":
+        return main_batch(args)
     w = workload(args.workload)
     prec = w["precision"]
     pts = int(np.prod(w["N"]))

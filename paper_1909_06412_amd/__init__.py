@@ -170,3 +170,106 @@ def from_workload(w: dict, precision=None, use_torch=True) -> MovingGrid:
     mg.set_scheme(w["split"], w["comp"], w["order"])
     mg.set_gaussian(w["q0"], w["p0"], w["sigma"])
     return mg
+
+
+class MovingGridBatch:
+    """Many independent wavepackets with their own grids, propagated by one
+    persistent kernel launch per mg_batch_step (wraps an mg_batch)."""
+
+    def __init__(self, shapes, dqs, inv_mass, hbar=1.0, precision="c64"):
+        shapes = [list(map(int, s)) for s in shapes]
+        self.B = len(shapes)
+        self.D = len(shapes[0])
+        self.shapes = shapes
+        self.precision = precision
+        lib = L.lib()
+        stream, _ = _torch_stream_and_alloc()
+        Narr = np.ascontiguousarray(np.asarray(shapes, dtype=np.int32).reshape(-1))
+        dq = L.f64(np.asarray(dqs, dtype=float).reshape(-1), self.B * self.D)
+        h = L.C.c_void_p()
+        st = lib.mg_batch_create(self.B, self.D, Narr.ctypes.data_as(L._ip), L.dptr(dq),
+                                 L.dptr(L.f64(inv_mass, self.D)), float(hbar), _PREC[precision],
+                                 stream, L.C.byref(h))
+        if st != 0:
+            raise L.MgError(st, "mg_batch_create: " + (lib.mg_last_error(None) or b"").decode())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            L.lib().mg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def points(self):
+        return int(L.lib().mg_batch_points(self.h))
+
+    def set_gaussian(self, q0, p0, sigma):
+        n = self.B * self.D
+        L.check(L.lib().mg_batch_set_gaussian(self.h, L.dptr(L.f64(q0, n)), L.dptr(L.f64(p0, n)),
+                                              L.dptr(L.f64(sigma, n))), self.h)
+
+    def set_potential(self, kind, params):
+        pr = potential_params(kind, params, self.D)
+        L.check(L.lib().mg_batch_set_potential(self.h, _POT[kind], L.dptr(pr) if pr.size else None,
+                                               int(pr.size)), self.h)
+
+    def set_scheme(self, split="TVT", comp="strang", order=2, gammas=None):
+        g = None if gammas is None else L.f64(gammas)
+        L.check(L.lib().mg_batch_set_scheme(self.h, _SPLIT[split], _COMP[comp], int(order), L.dptr(g),
+                                            0 if g is None else int(g.size)), self.h)
+
+    def step(self, dt, nsteps=1):
+        L.check(L.lib().mg_batch_step(self.h, float(dt), int(nsteps)), self.h)
+
+    def observables(self):
+        D = self.D
+        out = np.empty(self.B * (4 + 4 * D))
+        L.check(L.lib().mg_batch_observables(self.h, L.dptr(out)), self.h)
+        out = out.reshape(self.B, 4 + 4 * D)
+        return [dict(norm=o[0], q=o[1:1 + D].copy(), p=o[1 + D:1 + 2 * D].copy(),
+                     q_ctr=o[1 + 2 * D:1 + 3 * D].copy(), p_ctr=o[1 + 3 * D:1 + 4 * D].copy(),
+                     Ekin=o[1 + 4 * D], Epot=o[2 + 4 * D], E=o[1 + 4 * D] + o[2 + 4 * D], t=o[3 + 4 * D])
+                for o in out]
+
+    def get_state(self, idx):
+        N = self.shapes[idx]
+        psi = np.empty(N, dtype=np.complex128)
+        q = np.empty(self.D)
+        p = np.empty(self.D)
+        t = np.empty(1)
+        L.check(L.lib().mg_batch_get_state(self.h, int(idx), L.dptr(psi.view(np.float64).reshape(-1)),
+                                           L.dptr(q), L.dptr(p), L.dptr(t)), self.h)
+        return psi, q, p, float(t[0])
+
+    def set_state(self, idx, psi_phys, q_ctr, p_ctr, t=0.0):
+        a = np.ascontiguousarray(np.asarray(psi_phys, dtype=np.complex128).reshape(self.shapes[idx]))
+        L.check(L.lib().mg_batch_set_state(self.h, int(idx), L.dptr(a.view(np.float64).reshape(-1)),
+                                           L.dptr(L.f64(q_ctr, self.D)), L.dptr(L.f64(p_ctr, self.D)),
+                                           float(t)), self.h)
+
+    def adjoint(self, dt, nsteps, K, window, param_ids):
+        ids = np.ascontiguousarray(np.asarray(param_ids, dtype=np.int32))
+        J = np.empty(self.B)
+        g = np.empty(self.B * len(ids))
+        L.check(L.lib().mg_batch_adjoint(self.h, float(dt), int(nsteps), int(K), L.dptr(L.f64(window, 2)),
+                                         ids.ctypes.data_as(L._ip), int(ids.size), L.dptr(J), L.dptr(g)),
+                self.h)
+        return J, g.reshape(self.B, len(ids))
+
+
+def batch_from_workloads(ws, precision=None) -> MovingGridBatch:
+    """A batch from a list of workloads-module dicts sharing D, masses, potential and scheme."""
+    w0 = ws[0]
+    b = MovingGridBatch([w["N"] for w in ws], [w["dq"] for w in ws], w0["inv_mass"], w0["hbar"],
+                        precision or w0["precision"])
+    kind, par = w0["potential"]
+    b.set_potential(kind, par)
+    b.set_scheme(w0["split"], w0["comp"], w0["order"])
+    b.set_gaussian([w["q0"] for w in ws], [w["p0"] for w in ws], [w["sigma"] for w in ws])
+    return b

@@ -129,69 +129,28 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
     block_reduce<NTHR>(acc, nacc, tot, red);
   }
   if (threadIdx.x == 0) {
-    if (a.mode == FIN_T || a.mode == FIN_V || a.mode == FIN_NORM)
-      for (int k = 0; k < nacc; ++k) st.last[k] = tot[k];
     if (a.mode == FIN_T) {
-      const double n = tot[0];
-      bool bad = !(n > 0.0) || !isfinite(n);
-      for (int l = 0; l < D; ++l) {
-        const double pbar = st.p_c[l] + G.ax[l].dp * (tot[1 + l] / n);
-        const double d = a.h * G.ax[l].minv * pbar;
-        if (!isfinite(d) || fabs(d) > 0.5 * G.ax[l].n * G.ax[l].dq) bad = true;
-        st.delta[l] = d;
-        st.q_c[l] += d;
-      }
-      if (bad) st.err = 1;
+      fin_kinetic(G, st, tot, a.h);
     } else if (a.mode == FIN_REGRID) {
       for (int l = 0; l < D; ++l) {
         st.delta[l] = a.forced[l];
         st.q_c[l] += a.forced[l];
       }
     } else if (a.mode == FIN_V) {
-      const double n = tot[0];
-      bool bad = !(n > 0.0) || !isfinite(n);
-      for (int l = 0; l < D; ++l) {
-        const double gl = tot[1 + l] / n;
-        if (!isfinite(gl)) bad = true;
-        st.p_c[l] -= a.h * gl;
-      }
-      if (bad) st.err = 1;
+      fin_potential(G, st, tot, a.h);
     } else if (a.mode == FIN_OBSQ) {
       for (int k = 0; k < nacc; ++k) st.obs[k] = tot[k];
     } else if (a.mode == FIN_OBSP) {
       for (int k = 0; k < nacc; ++k) st.obs[MGK_NACC + k] = tot[k];
     } else if (a.mode == FIN_NORM) {
+      for (int k = 0; k < nacc; ++k) st.last[k] = tot[k];
       st.scale = tot[0] > 0.0 ? 1.0 / sqrt(tot[0]) : 1.0;
     }
   }
   __syncthreads();
   const double hbar = G.hbar;
-  if (a.mode == FIN_T || a.mode == FIN_REGRID) {
-    const double h = a.mode == FIN_T ? a.h : 0.0;
-    for (int l = 0; l < D; ++l) {
-      const AxisDesc& ax = G.ax[l];
-      for (int k = threadIdx.x; k < ax.n; k += NTHR) {
-        const double p = st.p_c[l] + (double)(k - ax.n / 2) * ax.dp;
-        const double phi = (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / hbar;
-        double s, c;
-        sincos(phi, &s, &c);
-        a.M[ax.tab_off + k] = C{(decltype(C().x))c, (decltype(C().x))(-s)};
-      }
-    }
-  }
-  if (a.mode == FIN_V || a.mode == FIN_BUILD_A) {
-    for (int l = 0; l < D; ++l) {
-      const AxisDesc& ax = G.ax[l];
-      const double inv_sqrt = 1.0 / sqrt((double)ax.n);
-      for (int j = threadIdx.x; j < ax.n; j += NTHR) {
-        const double phi = st.p_c[l] * (double)j * ax.dq / hbar;
-        double s, c;
-        sincos(phi, &s, &c);
-        const double sg = (j & 1) ? -inv_sqrt : inv_sqrt;
-        a.A[ax.tab_off + j] = C{(decltype(C().x))(sg * c), (decltype(C().x))(-sg * s)};
-      }
-    }
-  }
+  if (a.mode == FIN_T || a.mode == FIN_REGRID) build_M_tables<T, NTHR>(G, st, a.mode == FIN_T ? a.h : 0.0, a.M);
+  if (a.mode == FIN_V || a.mode == FIN_BUILD_A) build_A_tables<T, NTHR>(G, st, a.A);
   // Group-combined tables of the 16-point path: one FP64 angle sum per entry.
   if (G.fast16 && a.AG) {
     const bool doA = a.mode == FIN_V || a.mode == FIN_BUILD_A;
@@ -286,7 +245,8 @@ std::vector<int> radices(int n) {
 
 // Build the per-axis passes and the sweep plan of one packet.
 bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, double hbar, int tw_base,
-                std::map<int, int>& tw_offsets, int& tw_total, PacketGeom& G, std::string& err) {
+                std::map<int, int>& tw_offsets, int& tw_total, PacketGeom& G, std::string& err,
+                uint32_t tmax = MGK_TMAX) {
   memset(&G, 0, sizeof(G));
   G.D = D;
   G.hbar = hbar;
@@ -348,7 +308,7 @@ bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, d
     int a = b - 1;
     uint64_t LG = N[a];
     const uint64_t need = b == D ? 1 : std::min<uint64_t>(I, RUN);
-    while (a > 0 && LG * N[a - 1] * need <= MGK_TMAX) {
+    while (a > 0 && LG * N[a - 1] * need <= tmax) {
       --a;
       LG *= N[a];
     }
@@ -361,7 +321,7 @@ bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, d
     s.I = (uint32_t)I;
     if (b == D) {
       s.kind = 0;
-      s.ob = (uint32_t)std::min<uint64_t>(O, MGK_TMAX / LG);
+      s.ob = (uint32_t)std::min<uint64_t>(O, tmax / LG);
       s.r = 1;
       s.T = s.ob * s.LG;
       s.tiles_i = 1;
@@ -369,7 +329,7 @@ bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, d
     } else {
       s.kind = 1;
       s.ob = 1;
-      s.r = (uint32_t)std::min<uint64_t>(I, MGK_TMAX / LG);
+      s.r = (uint32_t)std::min<uint64_t>(I, tmax / LG);
       s.T = s.LG * s.r;
       s.tiles_i = (uint32_t)((I + s.r - 1) / s.r);
       s.ntiles = (uint32_t)(O * s.tiles_i);
@@ -486,7 +446,12 @@ struct ProfEntry {
   int cls;
 };
 
+#define MG_MAGIC_CTX 0x4d474358u
+#define MG_MAGIC_BATCH 0x4d474258u
+
 struct mg_ctx {
+  uint32_t magic = MG_MAGIC_CTX;
+  std::string err;
   int D = 0;
   mg_precision prec = MG_C128;
   hipStream_t stream = nullptr;
@@ -511,12 +476,12 @@ struct mg_ctx {
   int split = MG_TVT;
   std::vector<double> gam{1.0};
   int opt_graph = 0, opt_profile = 0, opt_renorm = 0, opt_engine = 0;
-  std::string err;
   std::vector<ProfEntry> prof_pending;
   std::map<int, std::pair<int64_t, double>> prof;  // class -> (launches, ms)
 };
 
 static thread_local std::string g_create_err;
+static const char* batch_error(const void* p);
 
 static mg_status fail(mg_ctx* c, mg_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -1205,7 +1170,10 @@ mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double
 
 const char* mg_last_error(const void* p) {
   if (!p) return g_create_err.empty() ? "null context" : g_create_err.c_str();
-  return ((const mg_ctx*)p)->err.c_str();
+  const uint32_t magic = *(const uint32_t*)p;
+  if (magic == MG_MAGIC_CTX) return ((const mg_ctx*)p)->err.c_str();
+  if (magic == MG_MAGIC_BATCH) return batch_error(p);
+  return "unknown handle";
 }
 
 }  // extern "C"

@@ -131,7 +131,7 @@ template <typename T, int R, typename C> __device__ __forceinline__ void dftR(C*
 // pre (first pass) multiplies inputs by a per-axis table at the natural index;
 // post (last pass) multiplies outputs by a per-axis table (or its conjugate).
 // ---------------------------------------------------------------------------
-template <typename T, int R, int NTHR>
+template <typename T, int R, int NTHR, int TM = MGK_TMAX>
 __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_t Tn, uint32_t n,
                                               uint32_t S, Div32 dS, const PassDesc& pd, bool inv,
                                               const typename CT<T>::type* __restrict__ tw,
@@ -139,7 +139,7 @@ __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_
                                               const typename CT<T>::type* __restrict__ post,
                                               bool post_conj) {
   typedef typename CT<T>::type C;
-  constexpr int MB = (MGK_TMAX + R * NTHR - 1) / (R * NTHR);
+  constexpr int MB = (TM + R * NTHR - 1) / (R * NTHR);
   const uint32_t nbl = n / R;
   const uint32_t nb = Tn / R;
   const uint32_t Ns = pd.Ns;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_
 }
 
 // FFT of every line of axis `ax` in the tile (all passes of that axis).
-template <typename T, int NTHR>
+template <typename T, int NTHR, int TM = MGK_TMAX>
 __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_t Tn,
                                               const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
                                               const typename CT<T>::type* tw,
@@ -204,11 +204,11 @@ __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_
     const typename CT<T>::type* pr = p == 0 ? pre : nullptr;
     const typename CT<T>::type* po = p == np - 1 ? post : nullptr;
     switch (pd.R) {
-      case 2: stockham_pass<T, 2, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
-      case 3: stockham_pass<T, 3, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
-      case 4: stockham_pass<T, 4, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
-      case 5: stockham_pass<T, 5, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
-      default: stockham_pass<T, 8, NTHR>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 2: stockham_pass<T, 2, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 3: stockham_pass<T, 3, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 4: stockham_pass<T, 4, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 5: stockham_pass<T, 5, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      default: stockham_pass<T, 8, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
     }
   }
 }

@@ -67,7 +67,7 @@ __device__ __forceinline__ bool tile_elem(const SweepDesc& sw, const TileOrigin&
 // Process one tile: load from src, transform the sweep's axes (forward with A pre-
 // multiplication, or inverse with M pre- and conj(A) post-multiplication), run the
 // pointwise epilogue and store to dst.  acc collects the epilogue's FP64 sums.
-template <typename T, int NTHR>
+template <typename T, int NTHR, int TM = MGK_TMAX>
 __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const PacketGeom& G, int si, uint32_t tile,
                                              const typename CT<T>::type* src, typename CT<T>::type* dst,
                                              const Tables<T>& tb, int dir, int epi, double h,
@@ -91,9 +91,9 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
     const AxisDesc& ax = G.ax[sw.a + ai];
     const C* tw = tb.tw + ax.tw_off;
     if (!inv) {
-      tile_axis_fft<T, NTHR>(lds, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off, nullptr, false);
+      tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off, nullptr, false);
     } else {
-      tile_axis_fft<T, NTHR>(lds, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
+      tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
                              tb.A + ax.tab_off, true);
     }
   }
@@ -112,6 +112,79 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
     else lds[t] = x;
   }
   __syncthreads();
+}
+
+}  // namespace mgk
+
+namespace mgk {
+
+// ---------------------------------------------------------------------------
+// Substep bookkeeping shared by the finalize kernel and the persistent batch
+// engine (one thread for the scalar part, the whole workgroup for the tables).
+// ---------------------------------------------------------------------------
+
+// Kinetic substep (Sec. II.G.2, Eqs. (49), (52)): <p> from the momentum-grid
+// sums tot = (sum w, sum w (k_l - N_l/2)), delta = h m^-1 <p>, q_ctr += delta.
+__device__ __forceinline__ void fin_kinetic(const PacketGeom& G, PacketState& st, const double* tot, double h) {
+  const double n = tot[0];
+  bool bad = !(n > 0.0) || !isfinite(n);
+  for (int l = 0; l < G.D; ++l) {
+    const double pbar = st.p_c[l] + G.ax[l].dp * (tot[1 + l] / n);
+    const double d = h * G.ax[l].minv * pbar;
+    if (!isfinite(d) || fabs(d) > 0.5 * G.ax[l].n * G.ax[l].dq) bad = true;
+    st.delta[l] = d;
+    st.q_c[l] += d;
+  }
+  for (int k = 0; k < G.D + 2; ++k) st.last[k] = tot[k];
+  if (bad) st.err = 1;
+}
+
+// Potential substep (Sec. II.G.1, Eq. (47)): p_ctr -= h <dV/dq> from
+// tot = (sum w, sum w dV/dq_l).
+__device__ __forceinline__ void fin_potential(const PacketGeom& G, PacketState& st, const double* tot, double h) {
+  const double n = tot[0];
+  bool bad = !(n > 0.0) || !isfinite(n);
+  for (int l = 0; l < G.D; ++l) {
+    const double gl = tot[1 + l] / n;
+    if (!isfinite(gl)) bad = true;
+    st.p_c[l] -= h * gl;
+  }
+  for (int k = 0; k < G.D + 2; ++k) st.last[k] = tot[k];
+  if (bad) st.err = 1;
+}
+
+// M_l(k) = exp(-i [h p^2 / (2 m_l) - delta_l p] / hbar), p = p_ctr + (k - N/2) dp
+template <typename T, int NT>
+__device__ __forceinline__ void build_M_tables(const PacketGeom& G, const PacketState& st, double h,
+                                               typename CT<T>::type* M) {
+  typedef typename CT<T>::type C;
+  for (int l = 0; l < G.D; ++l) {
+    const AxisDesc& ax = G.ax[l];
+    for (int k = threadIdx.x; k < ax.n; k += NT) {
+      const double p = st.p_c[l] + (double)(k - ax.n / 2) * ax.dp;
+      const double phi = (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / G.hbar;
+      double s, c;
+      sincos(phi, &s, &c);
+      M[ax.tab_off + k] = C{(decltype(C().x))c, (decltype(C().x))(-s)};
+    }
+  }
+}
+
+// A_l(j) = (-1)^j exp(-i p_ctr,l j dq_l / hbar) / sqrt(N_l)
+template <typename T, int NT>
+__device__ __forceinline__ void build_A_tables(const PacketGeom& G, const PacketState& st, typename CT<T>::type* A) {
+  typedef typename CT<T>::type C;
+  for (int l = 0; l < G.D; ++l) {
+    const AxisDesc& ax = G.ax[l];
+    const double inv_sqrt = 1.0 / sqrt((double)ax.n);
+    for (int j = threadIdx.x; j < ax.n; j += NT) {
+      const double phi = st.p_c[l] * (double)j * ax.dq / G.hbar;
+      double s, c;
+      sincos(phi, &s, &c);
+      const double sg = (j & 1) ? -inv_sqrt : inv_sqrt;
+      A[ax.tab_off + j] = C{(decltype(C().x))(sg * c), (decltype(C().x))(-sg * s)};
+    }
+  }
 }
 
 }  // namespace mgk
