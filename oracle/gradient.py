@@ -5,7 +5,8 @@ whole FP64 propagations.
 
 Objective (a "transmitted probability" past a dividing line on the final grid):
     J = sum_J W(q^J) |psi(q^J)|^2 prod_l dq_l,   W = 1 / (1 + exp(-(R_d - R)/w)),
-with R = rho - c r for the atom-diatom coordinates q = (r, rho).
+with R = rho - c r for the atom-diatom coordinates q = (r, rho), or R = q for a
+single coordinate.
 """
 from __future__ import annotations
 
@@ -15,8 +16,11 @@ from . import potentials, propagate
 
 
 def window(qs, R_d, w, c=0.5):
-    r, rho = qs
-    R = rho - c * r
+    if len(qs) == 1:
+        R = qs[0]
+    else:
+        r, rho = qs
+        R = rho - c * r
     return 1.0 / (1.0 + np.exp(-(R_d - R) / w))
 
 

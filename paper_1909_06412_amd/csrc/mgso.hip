@@ -1182,3 +1182,4 @@ const char* mg_last_error(const void* p) {
 // Entry points completed in mgso_batch.hip / mgso_adjoint.hip
 // ===========================================================================
 #include "mgso_batch.inc"
+#include "mgso_adjoint.inc"

@@ -278,6 +278,76 @@ __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double
   return V;
 }
 
+// Hessian-vector product out = (d^2 V / dq dq) v at one point (FP64).
+__device__ __forceinline__ void pot_hess_vec(const PotDesc& P, int D, const double* q, const double* v,
+                                             double* out) {
+  for (int l = 0; l < D; ++l) out[l] = 0.0;
+  switch (P.kind) {
+    case 1:
+      for (int l = 0; l < D; ++l) out[l] = P.p[l] * v[l];
+      break;
+    case 2: {
+      const double De = P.p[0], a = P.p[1], re = P.p[2], A = P.p[3], b = P.p[4], c = P.p[5];
+      const double e = exp(-a * (q[0] - re));
+      double h00 = 2.0 * De * a * a * e * (2.0 * e - 1.0);
+      if (D > 1) {
+        const double rep = A * exp(-b * (q[1] - c * q[0]));
+        h00 += b * b * c * c * rep;
+        const double h01 = -b * b * c * rep, h11 = b * b * rep;
+        out[0] = h00 * v[0] + h01 * v[1];
+        out[1] = h01 * v[0] + h11 * v[1];
+      } else {
+        out[0] = h00 * v[0];
+      }
+      break;
+    }
+    case 3: {
+      const double ka = P.p[0], la = P.p[1];
+      for (int l = 0; l < D; ++l) out[l] = ka * v[l];
+      for (int l = 0; l + 1 < D; ++l) {
+        const double x = q[l], y = q[l + 1];
+        // V_l = la (x^2 y - y^3/3): d2/dx2 = 2 la y, d2/dxdy = 2 la x, d2/dy2 = -2 la y
+        out[l] += 2.0 * la * y * v[l] + 2.0 * la * x * v[l + 1];
+        out[l + 1] += 2.0 * la * x * v[l] - 2.0 * la * y * v[l + 1];
+      }
+      break;
+    }
+    case 4:
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) out[a] += P.p[a * D + b] * v[b];
+      break;
+    default:
+      break;
+  }
+}
+
+// Derivatives with respect to potential parameter `id` (index into the
+// mg_set_potential list): returns dV/dtheta and fills dg = d(dV/dq)/dtheta.
+// Supported: harmonic k_l (ids 0..D-1); Morse+repulsion A (3) and b (4).
+__device__ __forceinline__ double pot_dtheta(const PotDesc& P, int D, const double* q, int id, double* dg) {
+  for (int l = 0; l < D; ++l) dg[l] = 0.0;
+  if (P.kind == 1 && id >= 0 && id < D) {
+    const double x = q[id] - P.p[D + id];
+    dg[id] = x;
+    return 0.5 * x * x;
+  }
+  if (P.kind == 2 && D == 2 && (id == 3 || id == 4)) {
+    const double A = P.p[3], b = P.p[4], c = P.p[5];
+    const double R = q[1] - c * q[0];
+    const double E = exp(-b * R);
+    if (id == 3) {  // V_rep = A E, grad = (b c A E, -b A E)
+      dg[0] = b * c * E;
+      dg[1] = -b * E;
+      return E;
+    }
+    // d/db: V -> -R A E; grad -> (c A E (1 - b R), -A E (1 - b R))
+    dg[0] = c * A * E * (1.0 - b * R);
+    dg[1] = -A * E * (1.0 - b * R);
+    return -R * A * E;
+  }
+  return 0.0;
+}
+
 // exp(-i phi) for the complex64 path without branches: quadrant reduction in FP64
 // (n = rint(2 phi / pi), r = phi - n pi/2 with pi/2 split in two parts so that the
 // reduction error stays near 1e-16 for |phi| < 1e6), then the Taylor series of

@@ -154,15 +154,16 @@ __device__ __forceinline__ void fin_potential(const PacketGeom& G, PacketState& 
 }
 
 // M_l(k) = exp(-i [h p^2 / (2 m_l) - delta_l p] / hbar), p = p_ctr + (k - N/2) dp
+// (sgn = -1 builds conj(M), used by the adjoint of the kinetic substep)
 template <typename T, int NT>
 __device__ __forceinline__ void build_M_tables(const PacketGeom& G, const PacketState& st, double h,
-                                               typename CT<T>::type* M) {
+                                               typename CT<T>::type* M, double sgn = 1.0) {
   typedef typename CT<T>::type C;
   for (int l = 0; l < G.D; ++l) {
     const AxisDesc& ax = G.ax[l];
     for (int k = threadIdx.x; k < ax.n; k += NT) {
       const double p = st.p_c[l] + (double)(k - ax.n / 2) * ax.dp;
-      const double phi = (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / G.hbar;
+      const double phi = sgn * (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / G.hbar;
       double s, c;
       sincos(phi, &s, &c);
       M[ax.tab_off + k] = C{(decltype(C().x))c, (decltype(C().x))(-s)};
