@@ -364,13 +364,14 @@ __device__ __forceinline__ float2 phase_poly(double phi) {
   const float sn = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
   const float cs = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320))));
   const int q = (int)n & 3;
-  // exp(i phi) = exp(i q pi/2) (cs + i sn)
-  float c, s;
-  if (q == 0) { c = cs; s = sn; }
-  else if (q == 1) { c = -sn; s = cs; }
-  else if (q == 2) { c = -cs; s = -sn; }
-  else { c = sn; s = -cs; }
-  return float2{c, -s};
+  // exp(i phi) = exp(i q pi/2) (cs + i sn): quadrant q swaps the pair when odd and
+  // negates cos for q = 1, 2 and sin for q = 2, 3 (selects and sign flips, no branches)
+  const bool odd = (q & 1) != 0;
+  const float c0 = odd ? sn : cs, s0 = odd ? cs : sn;
+  const uint32_t sc = (uint32_t)((q + 1) & 2) << 30, ss = (uint32_t)(q & 2) << 30;
+  const float c = __uint_as_float(__float_as_uint(c0) ^ sc);
+  const float ms = __uint_as_float(__float_as_uint(s0) ^ ss ^ 0x80000000u);  // -sin
+  return float2{c, ms};
 }
 
 // The same in FP64 for the complex128 path: Taylor series to x^17 / x^16 on

@@ -97,56 +97,79 @@ template <typename T, bool INV, typename C> __device__ __forceinline__ void dft1
 
 __device__ __forceinline__ uint32_t pad16(uint32_t t) { return t + (t >> 4); }
 
-// Lagrange weight of node i (nodes at line points 0, 5, 10, 15) at line point k:
-// a cubic through the four nodes reproduces any polynomial of degree <= 3.
-__host__ __device__ constexpr double lag4(int k, int i) {
-  const int nd[4] = {0, 5, 10, 15};
-  double num = 1.0, den = 1.0;
-  for (int j = 0; j < 4; ++j)
-    if (j != i) {
-      num *= (double)(k - nd[j]);
-      den *= (double)(nd[i] - nd[j]);
-    }
-  return num / den;
-}
-
 // Potentials that are polynomials of degree <= 3 in each coordinate (free,
-// harmonic, quadratic, Henon-Heiles): along a line of 16 points V and dV/dq are
-// cubics of the line coordinate, so four exact evaluations determine all 16.
-// (These are the only kinds a 16^D grid with D >= 3 can carry.)
+// harmonic, quadratic, Henon-Heiles): along a line of 16 points V is a cubic of
+// the line coordinate and each dV/dq_m a quadratic, so a Taylor expansion at the
+// line centre is exact.  (These are the only kinds a 16^D grid with D >= 3 can
+// carry.)
 static inline bool pot_is_cubic(int kind) { return kind != 2; }
 
 template <typename T> __device__ __forceinline__ typename CT<T>::type phase_t(double phi);
 template <> __device__ __forceinline__ float2 phase_t<float>(double phi) { return phase_poly(phi); }
 template <> __device__ __forceinline__ double2 phase_t<double>(double phi) { return phase_poly64(phi); }
 
-// Potential part of the line epilogue: evaluate V and dV/dq at line points
-// 0, 5, 10, 15 (coordinates from the fixed indices jfix and the line axis L),
-// accumulate sum_k w_k dV/dq(q_k) = sum_i u_i dV/dq(node i) into acc[1..D] and
-// return the node values Vn for the interpolation of V along the line.
+// Potential part of the line epilogue (Sec. II.G.1, Eqs. (45), (47)) for a line
+// along packet axis L whose other indices are jfix.  With u = x - x_c (x_c the
+// centre q_ctr,L, line point 8) and s = u / dq_L = k - 8, the moments of the
+// weights M0 = sum w, M1 = sum w s, M2 = sum w s^2 give
+//   sum_k w_k dV/dq_m(x_k) = b0_m M0 + b1_m dq M1 + b2_m dq^2 M2,
+// where dV/dq_m = b0_m + b1_m u + b2_m u^2 along the line, and
+//   V(s) = c0 + c1 s + c2 s^2 + c3 s^3,  c0 = V(x_c), c1 = b0_L dq,
+//   c2 = b1_L dq^2 / 2, c3 = b2_L dq^3 / 3.
+// b0 is the gradient at the line centre; b1, b2 are nonzero only where the
+// gradient depends on x (one entry for the harmonic kind, one column of K for
+// the quadratic kind, axes L-1, L, L+1 for Henon-Heiles).
 template <int PK>
-__device__ __forceinline__ void line_potential(int L, const int* jfix, const double* u, double* Vn,
-                                               const PacketGeom& G, const PacketState& st, const PotDesc& P,
-                                               double* acc) {
+__device__ __forceinline__ void line_model(int L, const int* jfix, double M0, double M1, double M2,
+                                           const PacketGeom& G, const PacketState& st, const PotDesc& P,
+                                           double* acc, double* cp) {
   const int D = G.D;
-  double q[MGK_MAXD], gr[MGK_MAXD];
+  double q[MGK_MAXD], g[MGK_MAXD];
 #pragma unroll
   for (int l = 0; l < MGK_MAXD; ++l)
-    if (l < D) q[l] = st.q_c[l] + (double)(jfix[l] - 8) * G.ax[l].dq;
-  const double qL0 = st.q_c[L] - 8.0 * G.ax[L].dq, dqL = G.ax[L].dq;
-#pragma unroll 1
-  for (int i = 0; i < 4; ++i) {
+    if (l < D) q[l] = l == L ? st.q_c[l] : st.q_c[l] + (double)(jfix[l] - 8) * G.ax[l].dq;
+  const double V0 = pot_eval<PK>(P, D, q, g);
+  const double d = G.ax[L].dq;
+  const double S1 = d * M1, S2 = d * d * M2;
+  double b0L = 0.0, b1L = 0.0, b2L = 0.0;
+  if (PK == 1) b1L = P.p[L];
+  if (PK == 4) b1L = P.p[L * D + L];
+  double xc = 0.0, ym = 0.0, yp = 0.0;
+  if (PK == 3) {
 #pragma unroll
-    for (int l = 0; l < MGK_MAXD; ++l)
-      if (l == L) q[l] = qL0 + (double)(5 * i) * dqL;
-    const double Vi = pot_eval<PK>(P, D, q, gr);
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (j == i) Vn[j] = Vi;
-#pragma unroll
-    for (int l = 0; l < MGK_MAXD; ++l)
-      if (l < D) acc[1 + l] += u[i] * gr[l];
+    for (int l = 0; l < MGK_MAXD; ++l) {
+      if (l == L) xc = q[l];
+      if (l + 1 == L) ym = q[l];
+      if (l == L + 1 && l < D) yp = q[l];
+    }
+    const double ka = P.p[0], la = P.p[1];
+    b1L = ka;
+    if (L + 1 < D) b1L += 2.0 * la * yp;
+    if (L >= 1) {
+      b1L -= 2.0 * la * xc;
+      b2L = -la;
+    }
   }
+#pragma unroll
+  for (int m = 0; m < MGK_MAXD; ++m) {
+    if (m >= D) continue;
+    double v = g[m] * M0;
+    if (m == L) {
+      b0L = g[m];
+      v += b1L * S1 + b2L * S2;
+    }
+    if (PK == 4 && m != L) v += P.p[m * D + L] * S1;
+    if (PK == 3) {
+      const double la = P.p[1];
+      if (m + 1 == L) v += 2.0 * la * ym * S1;
+      if (m == L + 1) v += 2.0 * la * xc * S1 + la * S2;
+    }
+    acc[1 + m] += v;
+  }
+  cp[0] = V0;
+  cp[1] = b0L * d;
+  cp[2] = 0.5 * b1L * d * d;
+  cp[3] = b2L * (1.0 / 3.0) * d * d * d;
 }
 
 // Epilogue on a line held in registers (strided tiles): moments (REDP) or the
@@ -159,16 +182,13 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
 #pragma unroll
   for (int l = 0; l < MGK_MAXD; ++l)
     if (l < D) jfix[l] = (int)((f >> (4 * (D - 1 - l))) & 15);
-  double wl = 0.0, ml = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+  double wl = 0.0, ml = 0.0, m2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const double w = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
     wl += w;
-    if (EPI == EPI_REDP) ml += w * (double)(k - 8);
-    if (EPI == EPI_V) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) u[i] += lag4(k, i) * w;
-    }
+    ml += w * (double)(k - 8);
+    if (EPI == EPI_V) m2 += w * (double)((k - 8) * (k - 8));
   }
   acc[0] += wl;
   if (EPI == EPI_REDP) {
@@ -177,12 +197,15 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
       if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
   }
   if (EPI == EPI_V) {
-    double Vn[4];
-    line_potential<PK>(L, jfix, u, Vn, G, st, P, acc);
+    double cp[4];
+    line_model<PK>(L, jfix, wl, ml, m2, G, st, P, acc, cp);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) cp[i] *= hh;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const double V = lag4(k, 0) * Vn[0] + lag4(k, 1) * Vn[1] + lag4(k, 2) * Vn[2] + lag4(k, 3) * Vn[3];
-      x[k] = cmul(x[k], phase_t<T>(hh * V));
+      const double sk = (double)(k - 8);
+      const double phi = cp[0] + sk * cp[1] + (sk * sk) * cp[2] + (sk * sk * sk) * cp[3];
+      x[k] = cmul(x[k], phase_t<T>(phi));
     }
   }
 }
@@ -302,7 +325,7 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
       __syncthreads();
-      double Vn[4] = {0.0, 0.0, 0.0, 0.0};
+      double cp[4] = {0.0, 0.0, 0.0, 0.0};
       if (EPI) {
         const int L = d.a;
         int jfix[MGK_MAXD];
@@ -310,17 +333,14 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
         for (int l = 0; l < MGK_MAXD; ++l)
           if (l < D) jfix[l] = (int)((f >> (4 * (D - 1 - l))) & 15);
-        double wl = 0.0, ml = 0.0, u[4] = {0.0, 0.0, 0.0, 0.0};
+        double wl = 0.0, ml = 0.0, m2 = 0.0;
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
           const C y = lds[pad16(t + 256 * m)];
           const double w = (double)y.x * (double)y.x + (double)y.y * (double)y.y;
           wl += w;
-          if (EPI == EPI_REDP) ml += w * (double)(m - 8);
-          if (EPI == EPI_V) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) u[i] += lag4(m, i) * w;
-          }
+          ml += w * (double)(m - 8);
+          if (EPI == EPI_V) m2 += w * (double)((m - 8) * (m - 8));
         }
         acc[0] += wl;
         if (EPI == EPI_REDP) {
@@ -328,15 +348,36 @@ void k_sweep16(S16Args<T> a) {
           for (int l = 0; l < MGK_MAXD; ++l)
             if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
         }
-        if (EPI == EPI_V) line_potential<PK>(L, jfix, u, Vn, G, *a.st, *a.pot, acc);
+        if (EPI == EPI_V) {
+          line_model<PK>(L, jfix, wl, ml, m2, G, *a.st, *a.pot, acc, cp);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) cp[i] *= hh;
+        }
       }
       C* __restrict__ tdst = dst + flat0;
+      // phase argument at s = m - 8 by forward differences of the cubic (three FP64
+      // adds per point; the 16-step drift is ~16 ulp of |phi|, far below the FP32
+      // rounding of the storage); the FP64 path evaluates the cubic directly
+      double ph = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+      if (EPI == EPI_V) {
+        ph = cp[0] - 8.0 * cp[1] + 64.0 * cp[2] - 512.0 * cp[3];
+        d1 = cp[1] - 15.0 * cp[2] + 169.0 * cp[3];
+        d2 = 2.0 * cp[2] - 42.0 * cp[3];
+        d3 = 6.0 * cp[3];
+      }
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
         C v = lds[pad16(t + 256 * m)];
         if (EPI == EPI_V) {
-          const double V = lag4(m, 0) * Vn[0] + lag4(m, 1) * Vn[1] + lag4(m, 2) * Vn[2] + lag4(m, 3) * Vn[3];
-          v = cmul(v, phase_t<T>(hh * V));
+          if constexpr (sizeof(T) == 4) {
+            v = cmul(v, phase_t<T>(ph));
+            ph += d1;
+            d1 += d2;
+            d2 += d3;
+          } else {
+            const double sm = (double)(m - 8);
+            v = cmul(v, phase_t<T>(cp[0] + sm * cp[1] + (sm * sm) * cp[2] + (sm * sm * sm) * cp[3]));
+          }
         }
         if (INV) v = cmulc(v, AG[t + 256 * m]);
         tdst[256 * m + t] = v;

@@ -212,3 +212,40 @@ def test_sixteen_point_sweep_kernels(D, precision):
     nsteps = 3 if D < 6 else 1
     compare(w, nsteps, precision, TOL128 if precision == "c128" else TOL64,
             tol_ctr=1e-12 if precision == "c128" else 1e-6)
+
+
+def _sixteen_point_case(kind, D):
+    """16^D packets for the potential kinds the 16-point kernels carry besides
+    Henon-Heiles; the potential substep uses the exact Taylor model of V along
+    each 16-point line."""
+    rng = np.random.default_rng(100 + D)
+    w = W.henon_heiles_8d(n=16, D=D, dq=0.6)
+    w["q0"] = rng.uniform(-1.0, 1.0, D).tolist()
+    w["p0"] = rng.uniform(-1.0, 1.0, D).tolist()
+    w["dt"] = 0.05
+    if kind == "harmonic":
+        w["potential"] = ("harmonic", {"k": rng.uniform(0.5, 2.5, D).tolist(),
+                                       "s": rng.uniform(-0.5, 0.5, D).tolist()})
+    elif kind == "quadratic":
+        B = rng.uniform(-0.3, 0.3, (D, D))
+        K = np.diag(rng.uniform(1.0, 2.5, D)) + B @ B.T
+        w["potential"] = ("quadratic", {"K": K.tolist(), "s": rng.uniform(-0.5, 0.5, D).tolist()})
+    else:
+        w["potential"] = ("free", {})
+    w["name"] = f"{kind}_{D}d_16^{D}"
+    return w
+
+
+@pytest.mark.parametrize("kind", ["harmonic", "quadratic", "free"])
+@pytest.mark.parametrize("D", [3, 4])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_sixteen_point_potential_kinds(kind, D, precision):
+    w = _sixteen_point_case(kind, D)
+    compare(w, 3, precision, TOL128 if precision == "c128" else TOL64,
+            tol_ctr=1e-12 if precision == "c128" else 1e-6)
+
+
+def test_sixteen_point_duschinsky_table_model():
+    """The paper's 3-D Duschinsky model (full K, unequal masses) on a 16^3 grid."""
+    w = W.duschinsky_3d(n=16, dq=0.6)
+    compare(w, 2, "c128", TOL128)
