@@ -540,7 +540,7 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
 
 template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, const S16Args<T>& a, int grid) {
   typedef typename CT<T>::type C;
-  const size_t lds = K > 1 ? (size_t)4352 * sizeof(C) : (size_t)(256 / 64) * MGK_NACC * sizeof(double);
+  const size_t lds = k16_lds_bytes<T>(K, INV);
   if constexpr (EPI == EPI_V) {
     switch (c->pot.kind) {
       case MG_POT_FREE: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 0>), dim3(grid), dim3(256), lds, c->stream, a); break;
@@ -768,15 +768,25 @@ static mg_status upload_state_scalars(mg_ctx* c, const double* q, const double* 
   return MG_OK;
 }
 
-template <int K> static hipError_t set_lds_attr_v(int bytes) {
-  hipError_t e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 0>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 3>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_sweep16<double, K, true, EPI_V, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+// Dynamic-LDS limit of every 16-point kernel instantiation of one precision.
+template <typename T, int K, bool INV, int EPI, int PK = -1> static hipError_t lds_attr16() {
+  return hipFuncSetAttribute((const void*)k_sweep16<T, K, INV, EPI, PK>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)k16_lds_bytes<T>(K, INV));
+}
+template <typename T, int K> static hipError_t lds_attr16_k() {
+  hipError_t e = lds_attr16<T, K, false, 0>();
+  if (e == hipSuccess) e = lds_attr16<T, K, false, EPI_REDP>();
+  if (e == hipSuccess) e = lds_attr16<T, K, true, 0>();
+  if (e == hipSuccess) e = lds_attr16<T, K, true, EPI_V, 0>();
+  if (e == hipSuccess) e = lds_attr16<T, K, true, EPI_V, 1>();
+  if (e == hipSuccess) e = lds_attr16<T, K, true, EPI_V, 3>();
+  if (e == hipSuccess) e = lds_attr16<T, K, true, EPI_V, 4>();
+  return e;
+}
+template <typename T> static hipError_t set_lds_attr16() {
+  hipError_t e = lds_attr16_k<T, 1>();
+  if (e == hipSuccess) e = lds_attr16_k<T, 2>();
+  if (e == hipSuccess) e = lds_attr16_k<T, 3>();
   return e;
 }
 
@@ -786,8 +796,6 @@ static int ilog2u(uint64_t v) {
   return (1ull << l) == v ? l : -1;
 }
 
-// The 16-point sweep kernels apply when every axis has 16 points and D >= 3; the
-// sweep plan then consists of 4096-point tiles with power-of-two runs.
 static void setup_fast16(mg_ctx* c) {
   PacketGeom& G = c->geom;
   G.fast16 = 0;
@@ -861,17 +869,9 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   if (e == hipSuccess) e = hipMalloc(&c->d_part, (size_t)MAX_BLOCKS * MGK_NACC * sizeof(double));
   if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, (size_t)c->geom.gtab_len * c->csize);
   if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, (size_t)c->geom.gtab_len * c->csize);
-  if (e == hipSuccess && c->geom.fast16 && prec == MG_C128) {
+  if (e == hipSuccess && c->geom.fast16) {
     where = "hipFuncSetAttribute";
-    const int bytes = 4352 * (int)sizeof(double2);
-    e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, false, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, false, EPI_REDP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, false, EPI_REDP>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 2, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_sweep16<double, 3, true, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess) e = set_lds_attr_v<2>(bytes);
-    if (e == hipSuccess) e = set_lds_attr_v<3>(bytes);
+    e = prec == MG_C128 ? set_lds_attr16<double>() : set_lds_attr16<float>();
   }
   if (e == hipSuccess) where = "hipMemcpy";
   if (e == hipSuccess) e = hipMemcpy(c->d_geom, &c->geom, sizeof(PacketGeom), hipMemcpyHostToDevice);

@@ -119,17 +119,42 @@ template <> __device__ __forceinline__ double2 phase_t<double>(double phi) { ret
 // b0 is the gradient at the line centre; b1, b2 are nonzero only where the
 // gradient depends on x (one entry for the harmonic kind, one column of K for
 // the quadratic kind, axes L-1, L, L+1 for Henon-Heiles).
+// Packet constants the epilogue needs, staged in LDS once per workgroup: reads of
+// global memory inside the tile loop cannot use the scalar cache (the loop
+// stores to the state), so each would be a vector load waited on in turn.
+struct LineCst {
+  double qc[MGK_MAXD], dq[MGK_MAXD], pc[MGK_MAXD];
+  double ihb;
+  PotDesc pot;
+};
+
+__device__ __forceinline__ void stage_line_cst(LineCst& lc, const PacketGeom& G, const PacketState& st,
+                                               const PotDesc& P) {
+  const uint32_t t = threadIdx.x;
+  if (t < MGK_MAXD) {
+    lc.qc[t] = st.q_c[t];
+    lc.dq[t] = G.ax[t].dq;
+    lc.pc[t] = st.p_c[t];
+  }
+  if (t < MGK_POT_MAXPAR) lc.pot.p[t] = P.p[t];
+  if (t == 0) {
+    lc.ihb = 1.0 / G.hbar;
+    lc.pot.kind = P.kind;
+    lc.pot.D = P.D;
+  }
+  __syncthreads();
+}
+
 template <int PK>
-__device__ __forceinline__ void line_model(int L, const int* jfix, double M0, double M1, double M2,
-                                           const PacketGeom& G, const PacketState& st, const PotDesc& P,
-                                           double* acc, double* cp) {
-  const int D = G.D;
+__device__ __forceinline__ void line_model(int L, const int* jfix, double M0, double M1, double M2, int D,
+                                           const LineCst& lc, double* acc, double* cp) {
+  const PotDesc& P = lc.pot;
   double q[MGK_MAXD], g[MGK_MAXD];
 #pragma unroll
   for (int l = 0; l < MGK_MAXD; ++l)
-    if (l < D) q[l] = l == L ? st.q_c[l] : st.q_c[l] + (double)(jfix[l] - 8) * G.ax[l].dq;
+    if (l < D) q[l] = l == L ? lc.qc[l] : lc.qc[l] + (double)(jfix[l] - 8) * lc.dq[l];
   const double V0 = pot_eval<PK>(P, D, q, g);
-  const double d = G.ax[L].dq;
+  const double d = lc.dq[L];
   const double S1 = d * M1, S2 = d * d * M2;
   double b0L = 0.0, b1L = 0.0, b2L = 0.0;
   if (PK == 1) b1L = P.p[L];
@@ -175,9 +200,8 @@ __device__ __forceinline__ void line_model(int L, const int* jfix, double M0, do
 // Epilogue on a line held in registers (strided tiles): moments (REDP) or the
 // potential substep (V) with weights w_k = |x_k|^2.
 template <typename T, int EPI, int PK>
-__device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, uint64_t f, const PacketGeom& G,
-                                              const PacketState& st, const PotDesc& P, double hh, double* acc) {
-  const int D = G.D;
+__device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, uint64_t f, int D, const LineCst& lc,
+                                              double hh, double* acc) {
   int jfix[MGK_MAXD];
 #pragma unroll
   for (int l = 0; l < MGK_MAXD; ++l)
@@ -198,7 +222,7 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
   }
   if (EPI == EPI_V) {
     double cp[4];
-    line_model<PK>(L, jfix, wl, ml, m2, G, st, P, acc, cp);
+    line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, cp);
 #pragma unroll
     for (int i = 0; i < 4; ++i) cp[i] *= hh;
 #pragma unroll
@@ -208,6 +232,19 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
       x[k] = cmul(x[k], phase_t<T>(phi));
     }
   }
+}
+
+// Dynamic LDS of k_sweep16, in complex elements: the tile (with the pad16 gaps)
+// when there are transposes, then (strided tiles) the group tables of the sweep:
+// the pre-multiplication (forward A, inverse M) and, inverse, the conj(A) factors
+// of the store.  The final FP64 reduction reuses the start of the buffer.
+__host__ __device__ constexpr uint32_t k16_lds_elems(int K, bool INV) {
+  return (K > 1 ? 4352u : 0u) + (K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u);
+}
+template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, bool INV) {
+  const size_t b = (size_t)k16_lds_elems(K, INV) * 2 * sizeof(T);
+  const size_t red = (size_t)(256 / 64) * MGK_NACC * sizeof(double);
+  return b > red ? b : red;
 }
 
 template <typename T, int K, bool INV, int EPI, int PK = -1>
@@ -231,16 +268,50 @@ void k_sweep16(S16Args<T> a) {
   C* __restrict__ dst = a.dst + off;
   const C* __restrict__ AG = a.AG + d.gtab_off;
   const C* __restrict__ MG = a.MG + d.gtab_off;
+  __shared__ LineCst lc;
+  if (EPI == EPI_V) stage_line_cst(lc, G, *a.st, *a.pot);
+  // Strided tiles keep the sweep's group tables (16^K entries) in LDS for the
+  // whole launch; the table index of a thread's points is the same in every tile.
+  C* __restrict__ ltab = lds + (K > 1 ? 4352 : 0);
+  C* __restrict__ lsto = ltab + (1u << (4 * K));
+  if constexpr (KIND == 1) {
+    for (uint32_t i = t; i < (1u << (4 * K)); i += 256) {
+      ltab[i] = INV ? MG[i] : AG[i];
+      if (INV) lsto[i] = AG[i];
+    }
+    __syncthreads();
+  }
+  // Loads are software-pipelined: the first-axis loads of the next tile are in
+  // flight while the current tile is transformed (strided tiles: issued as soon
+  // as the current tile's data has arrived; contiguous tiles: once the tile sits
+  // in LDS, so that they overlap the epilogue and the stores).  Each tile is read
+  // and written by one workgroup only, so this is safe in place.
+  auto tile_flat0 = [&](uint32_t tl) -> uint64_t {
+    if (KIND == 0) return (uint64_t)tl << 12;
+    const uint32_t o = tl >> d.ltiles_i;
+    const uint32_t ib = tl & (d.tiles_i - 1);
+    return ((uint64_t)o << (d.lLG + d.lI)) + ((uint64_t)ib << d.lr);
+  };
+  // (complex64 only: the complex128 kernels have no registers to spare)
+  constexpr bool PIPE = sizeof(T) == 4;
+  C xn[16];
+  auto load_first = [&](uint32_t tl) {
+    const uint32_t S0 = 1u << d.lS[0];
+    const uint32_t tau = ((t >> d.lS[0]) << (d.lS[0] + 4)) + (t & (S0 - 1));
+    const uint64_t ms0 = KIND == 0 ? (uint64_t)S0 : ((uint64_t)(S0 >> d.lr) << d.lI);
+    const uint32_t lane0 =
+        KIND == 0 ? tau : (uint32_t)(((uint64_t)(tau >> d.lr) << d.lI) + (tau & ((1u << d.lr) - 1)));
+    const C* __restrict__ ts0 = src + tile_flat0(tl);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const C* __restrict__ bk = ts0 + (uint64_t)k * ms0;
+      xn[k] = bk[lane0];
+    }
+  };
+  if (PIPE && blockIdx.x < d.ntiles) load_first(blockIdx.x);
 
   for (uint32_t tile = blockIdx.x; tile < d.ntiles; tile += gridDim.x) {
-    uint64_t flat0;
-    if (KIND == 0) {
-      flat0 = (uint64_t)tile << 12;
-    } else {
-      const uint32_t o = tile >> d.ltiles_i;
-      const uint32_t ib = tile & (d.tiles_i - 1);
-      flat0 = ((uint64_t)o << (d.lLG + d.lI)) + ((uint64_t)ib << d.lr);
-    }
+    const uint64_t flat0 = tile_flat0(tile);
     auto flat_of = [&](uint32_t tau) -> uint64_t {
       if (KIND == 0) return flat0 + tau;
       return flat0 + ((uint64_t)(tau >> d.lr) << d.lI) + (tau & ((1u << d.lr) - 1));
@@ -261,17 +332,13 @@ void k_sweep16(S16Args<T> a) {
     {
       // uniform (scalar) base per point k + a 32-bit per-lane offset: the loads
       // use scalar-base addressing and stay in flight together
-      const C* __restrict__ pre = INV ? MG : AG;
-      const uint64_t ms = mem_stride(S);
+      const C* __restrict__ pre = KIND == 1 ? ltab : (INV ? MG : AG);
       const uint32_t ts = tab_stride(S);
-      const uint32_t lane = (uint32_t)(flat_of(tau0) - flat0);
       const uint32_t glane = g_of(tau0);
-      const C* __restrict__ tsrc = src + flat0;
+      if (!PIPE) load_first(tile);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const C* __restrict__ bk = tsrc + (uint64_t)k * ms;
-        x[k] = bk[lane];
-      }
+      for (int k = 0; k < 16; ++k) x[k] = xn[k];
+      if (PIPE && KIND == 1 && tile + gridDim.x < d.ntiles) load_first(tile + gridDim.x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], pre[k * ts + glane]);
       dft16<T, INV>(x);
@@ -299,14 +366,14 @@ void k_sweep16(S16Args<T> a) {
       const uint32_t ts = tab_stride(S);
       const uint32_t glane = g_of(tau0);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) pv[k] = AG[k * ts + glane];
+      for (int k = 0; k < 16; ++k) pv[k] = lsto[k * ts + glane];
     }
     if (K > 1) dft16<T, INV>(x);
     if constexpr (KIND == 1) {
       // ---- strided tile: epilogue on the thread's line (packet axis L), store
       // 128-byte segments straight from registers
       const int L = d.a + e;
-      if (EPI) line_epilogue<T, EPI, PK>(x, L, flat_of(tau0), G, *a.st, *a.pot, hh, acc);
+      if (EPI) line_epilogue<T, EPI, PK>(x, L, flat_of(tau0), D, lc, hh, acc);
       const uint64_t ms = mem_stride(S);
       const uint32_t lane = (uint32_t)(flat_of(tau0) - flat0);
       C* __restrict__ tdst = dst + flat0;
@@ -325,6 +392,7 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
       __syncthreads();
+      if (PIPE && KIND == 0 && tile + gridDim.x < d.ntiles) load_first(tile + gridDim.x);
       double cp[4] = {0.0, 0.0, 0.0, 0.0};
       if (EPI) {
         const int L = d.a;
@@ -349,9 +417,22 @@ void k_sweep16(S16Args<T> a) {
             if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
         }
         if (EPI == EPI_V) {
-          line_model<PK>(L, jfix, wl, ml, m2, G, *a.st, *a.pot, acc, cp);
+          line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, cp);
 #pragma unroll
           for (int i = 0; i < 4; ++i) cp[i] *= hh;
+          if (INV) {
+            // conj(AG) of the store folded into the same phase: along the line
+            // (axis L, index m = s + 8) its angle is ang_t + beta m, times (-1)^m
+            // (a contiguous tile holds the innermost three axes L, L+1, L+2; the
+            // thread's fixed indices there are (t >> 4) & 15 and t & 15)
+            const int j1 = (int)((t >> 4) & 15u), j2 = (int)(t & 15u);
+            const double ang_t = M_PI * (double)((j1 & 1) + (j2 & 1)) -
+                                 (lc.pc[L + 1] * lc.dq[L + 1] * (double)j1 +
+                                  lc.pc[L + 2] * lc.dq[L + 2] * (double)j2) * lc.ihb;
+            const double beta = -lc.pc[L] * lc.dq[L] * lc.ihb;
+            cp[0] += ang_t + 8.0 * beta;
+            cp[1] += beta;
+          }
         }
       }
       C* __restrict__ tdst = dst + flat0;
@@ -378,8 +459,16 @@ void k_sweep16(S16Args<T> a) {
             const double sm = (double)(m - 8);
             v = cmul(v, phase_t<T>(cp[0] + sm * cp[1] + (sm * sm) * cp[2] + (sm * sm * sm) * cp[3]));
           }
+          if (INV) {
+            // |AG| = (1/sqrt(16))^K = 4^-K (exact power of two); (-1)^m from the line axis
+            const T mag = (T)(1.0 / (double)(1 << (2 * K)));
+            const T sg = (m & 1) ? -mag : mag;
+            v.x *= sg;
+            v.y *= sg;
+          }
+        } else if (INV) {
+          v = cmulc(v, AG[t + 256 * m]);
         }
-        if (INV) v = cmulc(v, AG[t + 256 * m]);
         tdst[256 * m + t] = v;
       }
       __syncthreads();
