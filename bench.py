@@ -24,6 +24,9 @@ import workloads as W  # noqa: E402
 
 METRIC = "grid-point-steps/sec, c64 vs FP64 at <=1e-6 err; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_1909_06412_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+POT_KIND = {"free": 0, "harmonic": 1, "morse_repulsion": 2, "henon_heiles": 3, "quadratic": 4}
 
 
 def log(msg):
@@ -86,6 +89,52 @@ def run_cpu_baseline(name):
             "sample": f"{desc}, FP64 NumPy, {dt:.1f} s"}
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources (sorted by name): counters measured on other
+    sources no longer describe the kernels."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".h", ".hip", ".inc")):
+            h.update(f.encode())
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def kernel_label(w, precision, cls):
+    """Kernel template name of a profiled sweep class (sweep, dir, epi, group axes)."""
+    _, d, epi, k = cls
+    t = "float" if precision == "c64" else "double"
+    fast16 = w["D"] >= 3 and all(n == 16 for n in w["N"]) and w["potential"][0] != "morse_repulsion"
+    if not fast16:
+        return f"k_sweep<{t}>"
+    pk = POT_KIND[w["potential"][0]] if epi == 4 else -1
+    return f"k_sweep16<{t}, {k}, {'true' if d else 'false'}, {epi}, {pk}>"
+
+
+def measured_traffic(w, precision, label):
+    """HBM bytes per launch of `label` from the committed rocprofv3 counter summary
+    of this workload (FETCH_SIZE and WRITE_SIZE, each scaled by what the counter
+    reads for a plain device copy of known size), or None when there is none or it
+    was taken on other kernel sources."""
+    path = os.path.join(PROFILES, f"pmc_traffic_{w['name'].replace('^', 'e')}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    src, table = None, {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("source_sha256"):
+                src = line.split()[1]
+            elif line.startswith("kernel "):
+                parts = [x.strip() for x in line[len("kernel "):].split("|")]
+                vals = dict(x.split(None, 1) for x in parts[1:])
+                table[parts[0]] = float(vals["traffic_bytes"])
+    if src != kernel_source_hash():
+        return None
+    return table.get(label)
+
+
 def timed_run(w, precision, steps, warmup, profile):
     import paper_1909_06412_amd as mg
     import torch
@@ -102,7 +151,7 @@ def timed_run(w, precision, steps, warmup, profile):
     m.step(w["dt"], steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    prof = m.profile_read(reset=True) if profile else None
+    prof = (m.profile_class(), *m.profile_read(reset=True)) if profile else None
     m.set_option(mg.MG_OPT_PROFILE, 0)
     obs = m.observables()
     log(f"{w['name']} {precision}: {steps} steps in {el:.3f} s; norm {obs['norm']:.15f}")
@@ -154,6 +203,27 @@ def main_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def calibrate_copy():
+    """A plain device copy of known size (4 GiB read + 4 GiB written per copy): the
+    reference for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes, and the
+    streaming bandwidth this device reaches with a simple kernel."""
+    import torch
+    n = 1 << 29
+    x = torch.ones(n, dtype=torch.complex64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    best = None
+    for i in range(4):
+        t0 = time.perf_counter()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+        log(f"copy {i}: {el * 1e3:.3f} ms")
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                      "best_ms": best * 1e3, "GB_s": 2 * n * 8 / best / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +232,8 @@ def main():
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time a plain 4 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)",
@@ -171,6 +243,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(3)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.workload == "c5":
         return main_batch(args)
     w = workload(args.workload)
@@ -181,9 +255,11 @@ def main():
     del m
     torch.cuda.empty_cache()
     value = pts * args.steps / el
-    launches, total_ms, bytes_per = prof
+    cls, launches, total_ms, bytes_per = prof
     avg_ms = total_ms / max(launches, 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    label = kernel_label(w, prec, cls)
+    traffic = measured_traffic(w, prec, label)
     out = {
         "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
@@ -193,8 +269,8 @@ def main():
                    "potential": w["potential"][0], "composition": w["comp"], "order": w["order"],
                    "split": w["split"], "dt": w["dt"], "precision": prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep (dominant sweep class)", "avg_ms": avg_ms,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": label, "sweep": cls[0], "avg_ms": avg_ms,
                      "launches": launches, "bytes_per_launch": bytes_per},
     }
     if not args.no_fp64 and prec == "c64":

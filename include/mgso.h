@@ -182,6 +182,12 @@ mg_status mg_set_option(mg_ctx* ctx, int option, int64_t value);
  * reset != 0 clears the counters after reading. */
 mg_status mg_profile_read(mg_ctx* ctx, int64_t* launches, double* total_ms,
                           double* bytes_per_launch, int reset);
+/* The kernel class that mg_profile_read reports (read it before a reset): sweep
+ * index (0 = the sweep over the innermost axes), dir (0 forward, 1 inverse), the
+ * epilogue flags of that sweep (1: momentum moments, 4: potential substep) and the
+ * number of axes the sweep transforms together.  All outputs -1 when nothing has
+ * been profiled.  Any output pointer may be NULL. */
+mg_status mg_profile_class(const mg_ctx* ctx, int* sweep, int* dir, int* epi, int* group_axes);
 
 /* Adjoint of a whole propagation (reverse sweep over the substeps, with the state
  * checkpointed every K steps and recomputed forward inside each block).

@@ -151,6 +151,12 @@ class MovingGrid:
                                         int(reset)), self.h)
         return n.value, ms.value, by.value
 
+    def profile_class(self):
+        """(sweep, dir, epi, group_axes) of the kernel class profile_read reports."""
+        v = [L.C.c_int() for _ in range(4)]
+        L.check(L.lib().mg_profile_class(self.h, *[L.C.byref(x) for x in v]), self.h)
+        return tuple(x.value for x in v)
+
     def adjoint(self, dt, nsteps, K, window, param_ids):
         ids = np.ascontiguousarray(np.asarray(param_ids, dtype=np.int32))
         J = np.empty(1)

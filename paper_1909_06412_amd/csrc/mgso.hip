@@ -1152,6 +1152,23 @@ mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
   return MG_OK;
 }
 
+mg_status mg_profile_class(const mg_ctx* c, int* sweep, int* dir, int* epi, int* group_axes) {
+  if (!c) return MG_EINVAL;
+  int best = -1;
+  double best_ms = -1;
+  for (auto& kv : c->prof)
+    if (kv.second.second > best_ms) {
+      best_ms = kv.second.second;
+      best = kv.first;
+    }
+  const int si = best < 0 ? -1 : best / 64;
+  if (sweep) *sweep = si;
+  if (dir) *dir = best < 0 ? -1 : (best / 32) & 1;
+  if (epi) *epi = best < 0 ? -1 : best & 31;
+  if (group_axes) *group_axes = si < 0 ? -1 : c->geom.sw[si].b - c->geom.sw[si].a;
+  return MG_OK;
+}
+
 mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double* bytes, int reset) {
   if (!c) return MG_EINVAL;
   int best = -1;
