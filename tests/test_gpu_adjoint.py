@@ -185,8 +185,9 @@ def test_batch_adjoint_matches_single_packets():
     for i, w in enumerate(ws):
         Ji, gi, _ = gpu_adjoint(w, [3, 4], 5, nsteps=25)
         print(f"[adjoint] batch packet {i}: J {J[i]:.15f} single {Ji:.15f}", flush=True)
-        assert abs(J[i] - Ji) < 1e-13
-        np.testing.assert_allclose(g[i], gi, rtol=1e-11, atol=1e-14)
+        # the batch kernel runs unfused substeps; the single-packet forward fuses them
+        assert abs(J[i] - Ji) < 1e-12
+        np.testing.assert_allclose(g[i], gi, rtol=1e-9, atol=1e-13)
 
 
 def test_unsupported_parameter_is_rejected():
@@ -198,3 +199,28 @@ def test_unsupported_parameter_is_rejected():
     with pytest.raises(mg.MgError):
         m.adjoint(w["dt"], 2, 0, (RD, WD), [3])    # K < 1
     m.close()
+
+
+def test_batch_adjoint_multi_tile_packets():
+    """Packets larger than one LDS tile of the batch kernel (complex64: 16384 points)
+    sweep through global memory tile by tile inside the persistent adjoint; complex64
+    and complex128 batches agree with each other and with single-packet adjoints."""
+    mg = _mg()
+    shapes = [(48, 64), (192, 96), (150, 162), (90, 72)]
+    ws = [morse_case(n1, n2, p0=p0) for (n1, n2), p0 in zip(shapes, [-19.2, -15.0, -25.0, -21.0])]
+    n, K = 30, 7
+    res = {}
+    for prec in ("c128", "c64"):
+        b = mg.batch_from_workloads(ws, precision=prec)
+        res[prec] = b.adjoint(ws[0]["dt"], n, K, (RD, WD), [3, 4])
+        b.close()
+    for i, w in enumerate(ws):
+        Ji, gi, _ = gpu_adjoint(w, [3, 4], K, nsteps=n)
+        J128, g128 = res["c128"][0][i], res["c128"][1][i]
+        J64, g64 = res["c64"][0][i], res["c64"][1][i]
+        print(f"[adjoint] batch {w['N']}: J {J128:.15f} single {Ji:.15f} c64 {J64:.9f}; "
+              f"grad {g128} c64 {g64}", flush=True)
+        assert abs(J128 - Ji) < 1e-12
+        np.testing.assert_allclose(g128, gi, rtol=1e-9, atol=1e-13)
+        assert abs(J64 - J128) < 1e-4 * abs(J128)
+        np.testing.assert_allclose(g64, g128, rtol=2e-3, atol=1e-6)
