@@ -84,7 +84,9 @@ typedef enum {
 typedef enum {
   MG_OPT_ENGINE = 1,         /* 0 = automatic, 1 = grid-wide sweeps (one kernel per sweep),
                                 2 = one workgroup per packet (persistent)                 */
-  MG_OPT_GRAPH = 2,          /* 1 = replay the steady-state step as a captured hipGraph   */
+  MG_OPT_GRAPH = 2,          /* 1 = capture the launches of mg_step / mg_batch_step once
+                                per (dt, nsteps) as a hipGraph and replay it; any set_*
+                                or option call re-captures on the next step              */
   MG_OPT_PROFILE = 3,        /* 1 = time every sweep kernel with HIP events               */
   MG_OPT_RENORMALIZE = 4     /* 1 = rescale to the FP64 norm after every potential substep
                                 (a deviation from the paper, off by default)              */

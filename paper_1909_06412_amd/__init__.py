@@ -116,8 +116,14 @@ class MovingGrid:
     # --- model -----------------------------------------------------------
     def set_potential(self, kind, params):
         pr = potential_params(kind, params, self.D)
+        self.set_potential_flat(kind, pr)
+
+    def set_potential_flat(self, kind, flat):
+        """mg_set_potential with the flat parameter list (see potential_params)."""
+        pr = L.f64(flat)
         L.check(L.lib().mg_set_potential(self.h, _POT[kind], L.dptr(pr) if pr.size else None,
                                          int(pr.size)), self.h)
+        self.potential = (kind, pr.copy())
 
     def set_scheme(self, split="TVT", comp="strang", order=2, gammas=None):
         g = None if gammas is None else L.f64(gammas)
@@ -222,13 +228,22 @@ class MovingGridBatch:
 
     def set_potential(self, kind, params):
         pr = potential_params(kind, params, self.D)
+        self.set_potential_flat(kind, pr)
+
+    def set_potential_flat(self, kind, flat):
+        """mg_batch_set_potential with the flat parameter list (see potential_params)."""
+        pr = L.f64(flat)
         L.check(L.lib().mg_batch_set_potential(self.h, _POT[kind], L.dptr(pr) if pr.size else None,
                                                int(pr.size)), self.h)
+        self.potential = (kind, pr.copy())
 
     def set_scheme(self, split="TVT", comp="strang", order=2, gammas=None):
         g = None if gammas is None else L.f64(gammas)
         L.check(L.lib().mg_batch_set_scheme(self.h, _SPLIT[split], _COMP[comp], int(order), L.dptr(g),
                                             0 if g is None else int(g.size)), self.h)
+
+    def set_option(self, option, value):
+        L.check(L.lib().mg_batch_set_option(self.h, int(option), int(value)), self.h)
 
     def step(self, dt, nsteps=1):
         L.check(L.lib().mg_batch_step(self.h, float(dt), int(nsteps)), self.h)
@@ -279,3 +294,52 @@ def batch_from_workloads(ws, precision=None) -> MovingGridBatch:
     b.set_scheme(w0["split"], w0["comp"], w0["order"])
     b.set_gaussian([w["q0"] for w in ws], [w["p0"] for w in ws], [w["sigma"] for w in ws])
     return b
+
+
+# ---------------------------------------------------------------------------
+# Autograd: the adjoint of a whole propagation as a differentiable function.
+# ---------------------------------------------------------------------------
+def _autograd_function():
+    import torch
+
+    class TransmittedProbability(torch.autograd.Function):
+        """J(theta): the window objective of mg_adjoint after `nsteps` steps of `dt`,
+        with the potential parameters `param_ids` (indices into the flat
+        mg_set_potential list) set to theta.  The forward pass runs the library's
+        adjoint (forward propagation with checkpoints every K steps, then the
+        reverse sweep) and keeps dJ/dtheta for the backward pass.  For a batch, J
+        has one entry per packet and the packets share theta."""
+
+        @staticmethod
+        def forward(ctx, theta, prop, dt, nsteps, K, window, param_ids):
+            kind, flat = prop.potential
+            flat = flat.copy()
+            th = theta.detach().to("cpu", torch.float64).numpy()
+            for i, pid in enumerate(param_ids):
+                flat[pid] = th[i]
+            prop.set_potential_flat(kind, flat)
+            J, g = prop.adjoint(dt, nsteps, K, window, list(param_ids))
+            ctx.save_for_backward(torch.as_tensor(np.asarray(g), dtype=torch.float64))
+            ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
+            return torch.as_tensor(np.asarray(J), dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            (g,) = ctx.saved_tensors
+            gth = (gJ.to(torch.float64).reshape(-1, 1) * g.reshape(gJ.numel(), -1)).sum(0)
+            return gth.to(ctx.theta_dtype).to(ctx.theta_device), None, None, None, None, None, None
+
+    return TransmittedProbability
+
+
+_TP = None
+
+
+def transmitted_probability(prop, theta, dt, nsteps, K, window, param_ids):
+    """Differentiable J(theta) (torch): see TransmittedProbability.  `prop` is a
+    MovingGrid or MovingGridBatch holding the initial state; the propagation stays
+    applied, so set the initial state again before the next evaluation."""
+    global _TP
+    if _TP is None:
+        _TP = _autograd_function()
+    return _TP.apply(theta, prop, float(dt), int(nsteps), int(K), tuple(window), tuple(int(i) for i in param_ids))

@@ -478,6 +478,13 @@ struct mg_ctx {
   int opt_graph = 0, opt_profile = 0, opt_renorm = 0, opt_engine = 0;
   std::vector<ProfEntry> prof_pending;
   std::map<int, std::pair<int64_t, double>> prof;  // class -> (launches, ms)
+  // captured step (MG_OPT_GRAPH): replayed while (dt, nsteps, version) match
+  uint64_t version = 0;  // bumped by everything that changes the launch sequence or its pointers
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gcap = nullptr;
+  double g_dt = 0.0;
+  int64_t g_n = -1;
+  uint64_t g_ver = ~0ull;
 };
 
 static thread_local std::string g_create_err;
@@ -723,6 +730,44 @@ template <typename T> static mg_status step_impl(mg_ctx* c, double dt, int64_t n
   return MG_OK;
 }
 
+// MG_OPT_GRAPH: capture the launches of mg_step(dt, nsteps) once (on a private
+// stream: the caller's may be the null stream, which cannot be captured) and
+// replay the instantiated graph on the caller's stream.  The sequence has only
+// kernel launches (no memset or copy nodes).
+static mg_status step_graph(mg_ctx* c, double dt, int64_t nsteps) {
+  if (!c->gexec || c->g_dt != dt || c->g_n != nsteps || c->g_ver != c->version) {
+    if (c->gexec) {
+      HIPCHK(c, hipGraphExecDestroy(c->gexec));
+      c->gexec = nullptr;
+    }
+    if (!c->gcap) HIPCHK(c, hipStreamCreateWithFlags(&c->gcap, hipStreamNonBlocking));
+    // the capture must not overtake work already queued on the caller's stream
+    HIPCHK(c, c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize());
+    hipStream_t user = c->stream;
+    c->stream = c->gcap;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->gcap, hipStreamCaptureModeThreadLocal);
+    mg_status r = MG_OK;
+    if (e == hipSuccess) {
+      r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
+      e = hipStreamEndCapture(c->gcap, &g);
+    }
+    c->stream = user;
+    if (r == MG_OK && e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (r) return r;
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return fail(c, MG_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    c->g_dt = dt;
+    c->g_n = nsteps;
+    c->g_ver = c->version;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  return MG_OK;
+}
+
 static mg_status sync_and_check(mg_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->opt_profile) {
@@ -916,6 +961,8 @@ void mg_destroy(mg_ctx* c) {
   hipFree(c->d_part);
   if (c->d_AG) hipFree(c->d_AG);
   if (c->d_MG) hipFree(c->d_MG);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->gcap) (void)hipStreamDestroy(c->gcap);
   delete c;
 }
 
@@ -925,6 +972,7 @@ void* mg_state_ptr(mg_ctx* c) { return c ? c->psi : nullptr; }
 
 mg_status mg_bind_buffers(mg_ctx* c, void* psi_dev, void* work_dev) {
   if (!c || !psi_dev) return fail(c, MG_EINVAL, "psi_dev is NULL");
+  ++c->version;
   if (((uintptr_t)psi_dev & 255) || ((uintptr_t)work_dev & 255)) return fail(c, MG_EINVAL, "buffers must be 256-byte aligned");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->psi_owned) hipFree(c->psi);
@@ -1022,6 +1070,7 @@ mg_status mg_get_state(mg_ctx* c, double* psi_phys, double* q, double* p, double
 
 mg_status mg_set_potential(mg_ctx* c, mg_pot kind, const double* params, int np) {
   if (!c) return MG_EINVAL;
+  ++c->version;
   PotDesc P;
   memset(&P, 0, sizeof(P));
   P.kind = kind;
@@ -1050,6 +1099,7 @@ mg_status mg_set_potential(mg_ctx* c, mg_pot kind, const double* params, int np)
 
 mg_status mg_set_scheme(mg_ctx* c, mg_split split, mg_comp comp, int order, const double* gammas, int ns) {
   if (!c) return MG_EINVAL;
+  ++c->version;
   if (split != MG_TVT && split != MG_VTV) return fail(c, MG_EINVAL, "unknown split");
   std::string e;
   std::vector<double> g = composition(comp, order, gammas, ns, e);
@@ -1064,7 +1114,9 @@ mg_status mg_step(mg_ctx* c, double dt, int64_t nsteps) {
   if (!c->has_state) return fail(c, MG_ESTATE, "no valid state (set_gaussian / set_state first)");
   if (!std::isfinite(dt) || nsteps < 0) return fail(c, MG_EINVAL, "bad dt or nsteps");
   if (nsteps == 0) return MG_OK;
-  mg_status r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
+  mg_status r;
+  if (c->opt_graph && !c->opt_profile) r = step_graph(c, dt, nsteps);
+  else r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
   if (r) return r;
   if ((r = sync_and_check(c))) return r;
   // advance t on the host side of the state (device copy kept consistent)
@@ -1142,6 +1194,7 @@ mg_status mg_regrid(mg_ctx* c, const double* new_q) {
 
 mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
   if (!c) return MG_EINVAL;
+  ++c->version;
   switch (option) {
     case MG_OPT_ENGINE: if (value < 0 || value > 2) return fail(c, MG_EINVAL, "engine 0..2"); c->opt_engine = (int)value; break;
     case MG_OPT_GRAPH: c->opt_graph = value != 0; break;

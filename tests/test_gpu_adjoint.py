@@ -224,3 +224,37 @@ def test_batch_adjoint_multi_tile_packets():
         np.testing.assert_allclose(g128, gi, rtol=1e-9, atol=1e-13)
         assert abs(J64 - J128) < 1e-4 * abs(J128)
         np.testing.assert_allclose(g64, g128, rtol=2e-3, atol=1e-6)
+
+
+def test_autograd_function():
+    """torch.autograd through the adjoint: the gradient equals mg_adjoint's, J at a
+    moved theta equals the oracle's objective there, and a batch's J (one entry
+    per packet, shared theta) back-propagates the weighted sum of the packets'
+    gradients."""
+    import torch
+    mg = _mg()
+    w = morse_case()
+    n, K = 40, 8
+    m = mg.from_workload(w)
+    theta = torch.tensor([9.5, 2.1], dtype=torch.float64, requires_grad=True)
+    J = mg.transmitted_probability(m, theta, w["dt"], n, K, (RD, WD), [3, 4])
+    J.backward()
+    m.close()
+    par = dict(w["potential"][1], A=9.5, b=2.1)
+    Jref = OG.run_objective(w, par, n, RD, WD)
+    wr = W.scaled(w, potential=("morse_repulsion", par))
+    _, gr, _ = gpu_adjoint(wr, [3, 4], K, nsteps=n)
+    print(f"[adjoint] autograd: J {J.item():.15f} oracle {Jref:.15f} grad {theta.grad.numpy()} adjoint {gr}",
+          flush=True)
+    assert abs(J.item() - Jref) < 1e-11
+    np.testing.assert_allclose(theta.grad.numpy(), gr, rtol=1e-13, atol=0)
+    ws = [morse_case(48, 64, p0=-19.2), morse_case(72, 90, p0=-16.0)]
+    b = mg.batch_from_workloads(ws, precision="c128")
+    th = torch.tensor([10.0, 2.0], dtype=torch.float64, requires_grad=True)
+    Jb = mg.transmitted_probability(b, th, ws[0]["dt"], 20, 5, (RD, WD), [3, 4])
+    (Jb * torch.tensor([1.0, -2.0], dtype=torch.float64)).sum().backward()
+    b.close()
+    b2 = mg.batch_from_workloads(ws, precision="c128")
+    _, g2 = b2.adjoint(ws[0]["dt"], 20, 5, (RD, WD), [3, 4])
+    b2.close()
+    np.testing.assert_allclose(th.grad.numpy(), g2[0] - 2.0 * g2[1], rtol=1e-12, atol=1e-16)
