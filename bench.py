@@ -158,10 +158,18 @@ def timed_run(w, precision, steps, warmup, profile):
     return m, el, prof, obs
 
 
-def batch_run(ws, precision, steps, warmup):
+def batch_run(ws, precision, steps, warmup, autotune=True):
     import paper_1909_06412_amd as mg
     import torch
     b = mg.batch_from_workloads(ws, precision=precision)
+    tuned = None
+    if autotune:
+        # the batch's own autotuner picks the launch shape (outside the timed region)
+        k, ms = b.autotune(ws[0]["dt"], 10)
+        tuned = {"threads": b.config(k)[0], "tile": b.config(k)[1],
+                 "probe_ms_per_step": {f"{t}x{l}": round(float(x), 4)
+                                       for (t, l), x in zip((b.config(i) for i in range(len(ms))), ms)}}
+        log(f"autotune: {tuned}")
     log(f"batch of {b.B} packets, {b.points} points, {precision}; warmup {warmup}")
     if warmup:
         b.step(ws[0]["dt"], warmup)
@@ -175,12 +183,12 @@ def batch_run(ws, precision, steps, warmup):
         f"..{max(o['norm'] for o in obs):.12f}")
     pts = b.points
     b.close()
-    return el, pts, obs
+    return el, pts, obs, tuned
 
 
 def main_batch(args):
     ws = W.morse_batch(precision="c64")
-    el, pts, obs = batch_run(ws, "c64", args.steps, args.warmup)
+    el, pts, obs, tuned = batch_run(ws, "c64", args.steps, args.warmup)
     value = pts * args.steps / el
     out = {
         "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
@@ -189,10 +197,11 @@ def main_batch(args):
         "data": "synthetic",
         "config": {"workload": "morse_batch_256_packets", "packets": len(ws), "points": pts,
                    "potential": "morse_repulsion", "composition": "strang", "order": 2, "split": "TVT",
-                   "dt": ws[0]["dt"], "precision": "c64", "launch": "one persistent kernel per call"},
+                   "dt": ws[0]["dt"], "precision": "c64", "launch": "one persistent kernel per call",
+                   "launch_shape": tuned},
     }
     if not args.no_fp64:
-        el2, _, obs2 = batch_run(W.morse_batch(precision="c128"), "c128", args.steps, args.warmup)
+        el2, _, obs2, _ = batch_run(W.morse_batch(precision="c128"), "c128", args.steps, args.warmup)
         d = max(abs(a["norm"] - b_["norm"]) for a, b_ in zip(obs, obs2))
         d = max(d, max(float(np.max(np.abs(a["q"] - b_["q"]))) for a, b_ in zip(obs, obs2)))
         out["fp64"] = {"value": pts * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,

@@ -236,6 +236,23 @@ mg_status mg_batch_adjoint(mg_batch* b, double dt, int64_t nsteps, int K,
                            const double* window, const int* param_ids, int nparams,
                            double* J_out, double* grad_out);
 mg_status mg_batch_set_option(mg_batch* b, int option, int64_t value);
+
+/* Launch shapes of the batch step kernel: MG_BATCH_CONFIGS pairs (threads per
+ * workgroup, points a workgroup keeps in LDS as one tile); index 0 is the default.
+ * A packet of at most `tile` points stays in LDS for a whole mg_batch_step call;
+ * larger packets sweep through global memory tile by tile.  mg_batch_config reads
+ * pair `index` for the batch's precision (MG_EINVAL out of range). */
+#define MG_BATCH_CONFIGS 4
+mg_status mg_batch_config(const mg_batch* b, int index, int* threads, int* tile);
+/* Use launch shape `index` for the following mg_batch_step calls (builds that
+ * shape's per-packet plans on first use).  The batched adjoint keeps index 0. */
+mg_status mg_batch_set_config(mg_batch* b, int index);
+/* The batch's own autotuner: times probe_steps steps of dt with every launch shape
+ * on the batch's current state (HIP events around the launch), restores that state
+ * exactly, and keeps the fastest shape.  ms_per_step[MG_BATCH_CONFIGS] (may be
+ * NULL) receives the measured times, chosen the index kept.  Synchronises;
+ * allocates a copy of the batch state for the duration of the call. */
+mg_status mg_batch_autotune(mg_batch* b, double dt, int64_t probe_steps, double* ms_per_step, int* chosen);
 /* Total points (sum over packets). */
 int64_t mg_batch_points(const mg_batch* b);
 

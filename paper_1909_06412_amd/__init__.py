@@ -245,6 +245,26 @@ class MovingGridBatch:
     def set_option(self, option, value):
         L.check(L.lib().mg_batch_set_option(self.h, int(option), int(value)), self.h)
 
+    N_CONFIGS = 4
+
+    def config(self, index):
+        """(threads per workgroup, tile points) of launch shape `index`."""
+        th, tl = L.C.c_int32(), L.C.c_int32()
+        L.check(L.lib().mg_batch_config(self.h, int(index), L.C.byref(th), L.C.byref(tl)), self.h)
+        return th.value, tl.value
+
+    def set_config(self, index):
+        L.check(L.lib().mg_batch_set_config(self.h, int(index)), self.h)
+
+    def autotune(self, dt, probe_steps=20):
+        """Time every launch shape on the current state (restored afterwards) and keep
+        the fastest: returns (chosen index, ms per step of each shape)."""
+        ms = np.zeros(self.N_CONFIGS)
+        ch = L.C.c_int32()
+        L.check(L.lib().mg_batch_autotune(self.h, float(dt), int(probe_steps), L.dptr(ms), L.C.byref(ch)),
+                self.h)
+        return ch.value, ms
+
     def step(self, dt, nsteps=1):
         L.check(L.lib().mg_batch_step(self.h, float(dt), int(nsteps)), self.h)
 

@@ -65,6 +65,9 @@ _SIGS = {
     "mg_batch_adjoint": (C.c_int, [_vp, C.c_double, C.c_int64, C.c_int, _dp, _ip, C.c_int, _dp,
                                    _dp]),
     "mg_batch_set_option": (C.c_int, [_vp, C.c_int, C.c_int64]),
+    "mg_batch_config": (C.c_int, [_vp, C.c_int, _ip, _ip]),
+    "mg_batch_set_config": (C.c_int, [_vp, C.c_int]),
+    "mg_batch_autotune": (C.c_int, [_vp, C.c_double, C.c_int64, _dp, _ip]),
     "mg_batch_points": (C.c_int64, [_vp]),
     "mg_last_error": (C.c_char_p, [_vp]),
 }

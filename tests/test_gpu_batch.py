@@ -98,3 +98,35 @@ def test_batch_matches_single_context_and_observables():
         np.testing.assert_allclose(obs[i]["q_ctr"], ob1["q_ctr"], atol=1e-12)
         m.close()
     b.close()
+
+
+def test_launch_shapes_and_autotune():
+    """Every launch shape of the batch step kernel (threads, LDS tile) propagates the
+    same physics: each agrees with the oracle packet by packet; the autotuner times
+    the shapes on the batch's own state and restores that state bit for bit."""
+    mg = _mg()
+    ws = _batch_workloads(precision="c64")
+    nsteps = 20
+    refs = [oracle_packet(w, nsteps).physical() for w in ws]
+    b = mg.batch_from_workloads(ws, precision="c64")
+    psi0 = [b.get_state(i) for i in range(len(ws))]
+    chosen, ms = b.autotune(ws[0]["dt"], 5)
+    print(f"[batch] autotune: shapes {[b.config(k) for k in range(b.N_CONFIGS)]} ms/step {ms} -> {chosen}",
+          flush=True)
+    assert 0 <= chosen < b.N_CONFIGS and np.all(ms > 0)
+    for i in range(len(ws)):
+        p, q, pc, t = b.get_state(i)
+        assert np.array_equal(p, psi0[i][0]) and np.array_equal(q, psi0[i][1])
+        assert np.array_equal(pc, psi0[i][2]) and t == psi0[i][3]
+    b.close()
+    for k in range(mg.MovingGridBatch.N_CONFIGS):
+        b = mg.batch_from_workloads(ws, precision="c64")
+        b.set_config(k)
+        b.step(ws[0]["dt"], nsteps)
+        worst = 0.0
+        for i, ref in enumerate(refs):
+            psi, *_ = b.get_state(i)
+            worst = max(worst, np.linalg.norm(psi - ref) / np.linalg.norm(ref))
+        print(f"[batch] shape {k} {b.config(k)}: worst packet error vs oracle {worst:.3e}", flush=True)
+        assert worst < 2e-5
+        b.close()
