@@ -88,8 +88,13 @@ typedef enum {
                                 per (dt, nsteps) as a hipGraph and replay it; any set_*
                                 or option call re-captures on the next step              */
   MG_OPT_PROFILE = 3,        /* 1 = time every sweep kernel with HIP events               */
-  MG_OPT_RENORMALIZE = 4     /* 1 = rescale to the FP64 norm after every potential substep
+  MG_OPT_RENORMALIZE = 4,    /* 1 = rescale to the FP64 norm after every potential substep
                                 (a deviation from the paper, off by default)              */
+  MG_OPT_GRID = 5            /* grid scheme (Sec. II.F-G): 0 = the time-reversible moving
+                                grid (default); 1 = fixed grid (centres held); 2 = naive
+                                adaptive grid: each step on the frozen grid, then re-centred
+                                on <q>, <p> (Eqs. (29)-(34); not time reversible).  Batches
+                                offer 0 and 1; the adjoint needs 0                        */
 } mg_option;
 
 typedef struct mg_ctx mg_ctx;

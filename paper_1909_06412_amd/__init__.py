@@ -16,7 +16,7 @@ from . import _lib as L
 from ._lib import (MgError, MG_C128, MG_C64, MG_POT_FREE, MG_POT_HARMONIC,  # noqa: F401
                    MG_POT_MORSE_REP, MG_POT_HENON_HEILES, MG_POT_QUADRATIC, MG_TVT, MG_VTV,
                    MG_COMP_STRANG, MG_COMP_SUZUKI, MG_COMP_TRIPLE_JUMP, MG_COMP_USER,
-                   MG_OPT_ENGINE, MG_OPT_GRAPH, MG_OPT_PROFILE, MG_OPT_RENORMALIZE, MG_EUNSTABLE,
+                   MG_OPT_ENGINE, MG_OPT_GRAPH, MG_OPT_PROFILE, MG_OPT_RENORMALIZE, MG_OPT_GRID, MG_EUNSTABLE,
                    MG_EINVAL, MG_ESTATE)
 
 _POT = {"free": MG_POT_FREE, "harmonic": MG_POT_HARMONIC, "morse_repulsion": MG_POT_MORSE_REP,

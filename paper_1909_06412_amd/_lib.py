@@ -16,7 +16,7 @@ MG_C128, MG_C64 = 0, 1
 MG_POT_FREE, MG_POT_HARMONIC, MG_POT_MORSE_REP, MG_POT_HENON_HEILES, MG_POT_QUADRATIC = 0, 1, 2, 3, 4
 MG_TVT, MG_VTV = 0, 1
 MG_COMP_STRANG, MG_COMP_SUZUKI, MG_COMP_TRIPLE_JUMP, MG_COMP_USER = 0, 1, 2, 3
-MG_OPT_ENGINE, MG_OPT_GRAPH, MG_OPT_PROFILE, MG_OPT_RENORMALIZE = 1, 2, 3, 4
+MG_OPT_ENGINE, MG_OPT_GRAPH, MG_OPT_PROFILE, MG_OPT_RENORMALIZE, MG_OPT_GRID = 1, 2, 3, 4, 5
 MG_MAX_DIM = 8
 
 _STATUS = {0: "MG_OK", -1: "MG_EINVAL", -2: "MG_ENOMEM", -3: "MG_EDEVICE", -4: "MG_EUNSTABLE",

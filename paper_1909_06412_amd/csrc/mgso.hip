@@ -95,7 +95,9 @@ enum : int {
   FIN_OBSQ = 4,     // store position-grid sums
   FIN_OBSP = 5,     // store momentum-grid sums
   FIN_BUILD_A = 6,  // only rebuild the A tables from p_ctr
-  FIN_NORM = 7      // scale = 1/sqrt(sum w) for a following renormalisation pass
+  FIN_NORM = 7,     // scale = 1/sqrt(sum w) for a following renormalisation pass
+  FIN_NAIVE_A = 8,  // naive re-centring: p_ctr = <p>, delta = <q> - q_ctr (from the obs sums), A tables
+  FIN_NAIVE_M = 9   // naive re-centring: q_ctr += delta, M tables of the shift (h = 0)
 };
 
 template <typename T> struct FinArgs {
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
   const int nacc = D + 2;
   __shared__ double tot[MGK_NACC];
   __shared__ double red[(NTHR / 64) * MGK_NACC];
-  if (a.mode != FIN_BUILD_A && a.mode != FIN_REGRID) {
+  if (a.mode != FIN_BUILD_A && a.mode != FIN_REGRID && a.mode != FIN_NAIVE_A && a.mode != FIN_NAIVE_M) {
     double acc[MGK_NACC];
     for (int k = 0; k < nacc; ++k) acc[k] = 0.0;
     for (int b = threadIdx.x; b < a.nblk; b += NTHR)
@@ -145,16 +147,32 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
     } else if (a.mode == FIN_NORM) {
       for (int k = 0; k < nacc; ++k) st.last[k] = tot[k];
       st.scale = tot[0] > 0.0 ? 1.0 / sqrt(tot[0]) : 1.0;
+    } else if (a.mode == FIN_NAIVE_A) {
+      // Eqs. (29)-(34): the new centres are the expectation values of the state
+      // propagated on the frozen grid (position sums in obs[0..], momentum sums,
+      // taken on the p-grid at the old p_ctr, in obs[MGK_NACC..])
+      const double nq = st.obs[0], np_ = st.obs[MGK_NACC];
+      bool bad = !(nq > 0.0) || !(np_ > 0.0);
+      for (int l = 0; l < D; ++l) {
+        const double dl = G.ax[l].dq * st.obs[1 + l] / nq;
+        const double pl = st.p_c[l] + G.ax[l].dp * st.obs[MGK_NACC + 1 + l] / np_;
+        if (!isfinite(dl) || !isfinite(pl) || fabs(dl) > 0.5 * G.ax[l].n * G.ax[l].dq) bad = true;
+        st.delta[l] = dl;
+        st.p_c[l] = pl;
+      }
+      if (bad) st.err = 1;
+    } else if (a.mode == FIN_NAIVE_M) {
+      for (int l = 0; l < D; ++l) st.q_c[l] += st.delta[l];
     }
   }
   __syncthreads();
   const double hbar = G.hbar;
-  if (a.mode == FIN_T || a.mode == FIN_REGRID) build_M_tables<T, NTHR>(G, st, a.mode == FIN_T ? a.h : 0.0, a.M);
-  if (a.mode == FIN_V || a.mode == FIN_BUILD_A) build_A_tables<T, NTHR>(G, st, a.A);
+  const bool doM = a.mode == FIN_T || a.mode == FIN_REGRID || a.mode == FIN_NAIVE_M;
+  const bool doA = a.mode == FIN_V || a.mode == FIN_BUILD_A || a.mode == FIN_NAIVE_A;
+  if (doM) build_M_tables<T, NTHR>(G, st, a.mode == FIN_T ? a.h : 0.0, a.M);
+  if (doA) build_A_tables<T, NTHR>(G, st, a.A);
   // Group-combined tables of the 16-point path: one FP64 angle sum per entry.
   if (G.fast16 && a.AG) {
-    const bool doA = a.mode == FIN_V || a.mode == FIN_BUILD_A;
-    const bool doM = a.mode == FIN_T || a.mode == FIN_REGRID;
     if (doA || doM) {
       const double h = a.mode == FIN_T ? a.h : 0.0;
       for (int si = 0; si < G.nsweeps; ++si) {
@@ -476,6 +494,7 @@ struct mg_ctx {
   int split = MG_TVT;
   std::vector<double> gam{1.0};
   int opt_graph = 0, opt_profile = 0, opt_renorm = 0, opt_engine = 0;
+  int grid_mode = 0;  // MG_OPT_GRID: 0 moving (Sec. II.G), 1 fixed, 2 naive re-centring (Sec. II.F)
   std::vector<ProfEntry> prof_pending;
   std::map<int, std::pair<int64_t, double>> prof;  // class -> (launches, ms)
   // captured step (MG_OPT_GRAPH): replayed while (dt, nsteps, version) match
@@ -730,6 +749,33 @@ template <typename T> static mg_status step_impl(mg_ctx* c, double dt, int64_t n
   return MG_OK;
 }
 
+// The naive adaptive grid (Sec. II.F, Eqs. (29)-(34)): each step runs on the
+// frozen grid, then the grid is re-centred on the new expectation values: p_ctr
+// moves to <p> (taken on the p-grid at the old p_ctr) and the state is shifted by
+// <q> - q_ctr by trigonometric interpolation on the p-grid at the new p_ctr.
+template <typename T> static mg_status naive_recentre(mg_ctx* c) {
+  mg_status r;
+  int nb = 0;
+  if ((r = launch_pointwise<T>(c, EPI_REDQ, 0.0, &nb))) return r;
+  if ((r = launch_finalize<T>(c, FIN_OBSQ, 0.0, nb, nullptr))) return r;
+  if ((r = launch_finalize<T>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
+  if ((r = forward_transform<T>(c, c->psi, c->work, EPI_REDP, &nb))) return r;
+  if ((r = launch_finalize<T>(c, FIN_OBSP, 0.0, nb, nullptr))) return r;
+  if ((r = launch_finalize<T>(c, FIN_NAIVE_A, 0.0, 0, nullptr))) return r;
+  if ((r = forward_transform<T>(c, c->psi, c->psi, 0, &nb))) return r;
+  if ((r = launch_finalize<T>(c, FIN_NAIVE_M, 0.0, 0, nullptr))) return r;
+  return inverse_transform<T>(c, c->psi, 0, 0.0, &nb);
+}
+
+// The launches of mg_step(dt, nsteps) for the context's grid mode.
+template <typename T> static mg_status step_body(mg_ctx* c, double dt, int64_t nsteps) {
+  if (c->grid_mode != 2) return step_impl<T>(c, dt, nsteps);
+  mg_status r;
+  for (int64_t s = 0; s < nsteps; ++s)
+    if ((r = step_impl<T>(c, dt, 1)) || (r = naive_recentre<T>(c))) return r;
+  return MG_OK;
+}
+
 // MG_OPT_GRAPH: capture the launches of mg_step(dt, nsteps) once (on a private
 // stream: the caller's may be the null stream, which cannot be captured) and
 // replay the instantiated graph on the caller's stream.  The sequence has only
@@ -749,7 +795,7 @@ static mg_status step_graph(mg_ctx* c, double dt, int64_t nsteps) {
     hipError_t e = hipStreamBeginCapture(c->gcap, hipStreamCaptureModeThreadLocal);
     mg_status r = MG_OK;
     if (e == hipSuccess) {
-      r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
+      r = c->prec == MG_C64 ? step_body<float>(c, dt, nsteps) : step_body<double>(c, dt, nsteps);
       e = hipStreamEndCapture(c->gcap, &g);
     }
     c->stream = user;
@@ -809,6 +855,7 @@ static mg_status upload_state_scalars(mg_ctx* c, const double* q, const double* 
   }
   st.t = t;
   st.scale = 1.0;
+  st.fixed = c->grid_mode != 0;
   HIPCHK(c, hipMemcpyAsync(c->d_st, &st, sizeof(st), hipMemcpyHostToDevice, c->stream));
   return MG_OK;
 }
@@ -1116,7 +1163,7 @@ mg_status mg_step(mg_ctx* c, double dt, int64_t nsteps) {
   if (nsteps == 0) return MG_OK;
   mg_status r;
   if (c->opt_graph && !c->opt_profile) r = step_graph(c, dt, nsteps);
-  else r = c->prec == MG_C64 ? step_impl<float>(c, dt, nsteps) : step_impl<double>(c, dt, nsteps);
+  else r = c->prec == MG_C64 ? step_body<float>(c, dt, nsteps) : step_body<double>(c, dt, nsteps);
   if (r) return r;
   if ((r = sync_and_check(c))) return r;
   // advance t on the host side of the state (device copy kept consistent)
@@ -1200,6 +1247,17 @@ mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
     case MG_OPT_GRAPH: c->opt_graph = value != 0; break;
     case MG_OPT_PROFILE: c->opt_profile = value != 0; break;
     case MG_OPT_RENORMALIZE: c->opt_renorm = value != 0; break;
+    case MG_OPT_GRID: {
+      if (value < 0 || value > 2) return fail(c, MG_EINVAL, "grid mode 0..2");
+      if (value == 2) {
+        mg_status r = ensure_work(c);
+        if (r) return r;
+      }
+      c->grid_mode = (int)value;
+      const int32_t fx = value != 0;
+      HIPCHK(c, hipMemcpy(&c->d_st->fixed, &fx, sizeof(fx), hipMemcpyHostToDevice));
+      break;
+    }
     default: return fail(c, MG_EINVAL, "unknown option");
   }
   return MG_OK;

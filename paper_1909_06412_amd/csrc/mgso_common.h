@@ -123,7 +123,7 @@ struct PacketState {
   double t;
   double scale;           // renormalisation factor for the next pointwise pass
   int32_t err;
-  int32_t pad;
+  int32_t fixed;          // 1: grid centres held (fixed grid; the naive scheme between re-centrings)
 };
 
 #define MGK_POT_MAXPAR 24

@@ -125,9 +125,17 @@ namespace mgk {
 
 // Kinetic substep (Sec. II.G.2, Eqs. (49), (52)): <p> from the momentum-grid
 // sums tot = (sum w, sum w (k_l - N_l/2)), delta = h m^-1 <p>, q_ctr += delta.
+// With st.fixed the grid stays where it is (delta = 0): the fixed-grid propagation
+// that the naive scheme (Sec. II.F, Eqs. (29)-(34)) re-centres after each step.
 __device__ __forceinline__ void fin_kinetic(const PacketGeom& G, PacketState& st, const double* tot, double h) {
   const double n = tot[0];
   bool bad = !(n > 0.0) || !isfinite(n);
+  if (st.fixed) {
+    for (int l = 0; l < G.D; ++l) st.delta[l] = 0.0;
+    for (int k = 0; k < G.D + 2; ++k) st.last[k] = tot[k];
+    if (bad) st.err = 1;
+    return;
+  }
   for (int l = 0; l < G.D; ++l) {
     const double pbar = st.p_c[l] + G.ax[l].dp * (tot[1 + l] / n);
     const double d = h * G.ax[l].minv * pbar;
@@ -147,7 +155,7 @@ __device__ __forceinline__ void fin_potential(const PacketGeom& G, PacketState& 
   for (int l = 0; l < G.D; ++l) {
     const double gl = tot[1 + l] / n;
     if (!isfinite(gl)) bad = true;
-    st.p_c[l] -= h * gl;
+    if (!st.fixed) st.p_c[l] -= h * gl;
   }
   for (int k = 0; k < G.D + 2; ++k) st.last[k] = tot[k];
   if (bad) st.err = 1;
