@@ -196,6 +196,19 @@ mg_status mg_profile_read(mg_ctx* ctx, int64_t* launches, double* total_ms,
  * been profiled.  Any output pointer may be NULL. */
 mg_status mg_profile_class(const mg_ctx* ctx, int* sweep, int* dir, int* epi, int* group_axes);
 
+/* Autocorrelation <psi_0|psi_t> (Sec. III.C): psi_0 is the Gaussian of
+ * mg_set_gaussian with these parameters (q0, p0, sigma each [D]), evaluated
+ * analytically on the current (moved) grid; the inner product is Eq. (28).
+ * out[2] = (Re, Im), reduced in FP64.  Synchronises. */
+mg_status mg_autocorrelation(mg_ctx* ctx, const double* q0, const double* p0, const double* sigma,
+                             double* out);
+/* Spectrum from an autocorrelation series (Sec. III.C, Fig. 9): for each energy E_k,
+ * out[k] = Re integral_0^T <psi_0|psi_t> exp(-(t/t_damp)^2) exp(i E_k t / hbar) dt by the
+ * trapezoidal rule over the n samples times[n], acf[2n] (Re, Im interleaved).  Host
+ * arithmetic on the caller's arrays; no device work. */
+mg_status mg_spectrum(const double* times, const double* acf, int n, const double* energies, int ne,
+                      double t_damp, double hbar, double* out);
+
 /* Adjoint of a whole propagation (reverse sweep over the substeps, with the state
  * checkpointed every K steps and recomputed forward inside each block).
  * Objective on the final grid: J = sum_J W(q^J) |c_J|^2 with

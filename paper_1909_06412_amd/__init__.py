@@ -157,6 +157,13 @@ class MovingGrid:
                                         int(reset)), self.h)
         return n.value, ms.value, by.value
 
+    def autocorrelation(self, q0, p0, sigma):
+        """<psi_0|psi_t> with psi_0 the Gaussian (q0, p0, sigma) on the current grid."""
+        out = np.zeros(2)
+        L.check(L.lib().mg_autocorrelation(self.h, L.dptr(L.f64(q0, self.D)), L.dptr(L.f64(p0, self.D)),
+                                           L.dptr(L.f64(sigma, self.D)), L.dptr(out)), self.h)
+        return complex(out[0], out[1])
+
     def profile_class(self):
         """(sweep, dir, epi, group_axes) of the kernel class profile_read reports."""
         v = [L.C.c_int() for _ in range(4)]
@@ -314,6 +321,19 @@ def batch_from_workloads(ws, precision=None) -> MovingGridBatch:
     b.set_scheme(w0["split"], w0["comp"], w0["order"])
     b.set_gaussian([w["q0"] for w in ws], [w["p0"] for w in ws], [w["sigma"] for w in ws])
     return b
+
+
+def spectrum(times, acf, energies, t_damp=30.0, hbar=1.0):
+    """Re int <psi_0|psi_t> exp(-(t/t_damp)^2) exp(i E t / hbar) dt (mg_spectrum)."""
+    t = L.f64(times)
+    a = np.ascontiguousarray(np.asarray(acf, dtype=np.complex128).reshape(-1)).view(np.float64)
+    e = L.f64(energies)
+    out = np.zeros(e.size)
+    st = L.lib().mg_spectrum(L.dptr(t), L.dptr(a), int(t.size), L.dptr(e), int(e.size), float(t_damp),
+                             float(hbar), L.dptr(out))
+    if st != 0:
+        raise MgError(st, "mg_spectrum: bad arguments")
+    return out
 
 
 # ---------------------------------------------------------------------------

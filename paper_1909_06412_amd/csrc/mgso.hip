@@ -234,6 +234,50 @@ __global__ __launch_bounds__(NTHR) void k_init_gaussian(GaussArgs a, typename CT
   }
 }
 
+// Autocorrelation <psi_0|psi_t> (Sec. III.C) with psi_0 the Gaussian of Eq. (62)
+// evaluated analytically on the current grid.  psi_0 is a product of per-axis
+// factors: tab[l][j] = (pi sigma_l^2)^(-1/4) sqrt(dq_l) exp(-x^2/(2 sigma_l^2) + i p0_l x / hbar),
+// x = q_ctr,l + (j - N_l/2) dq_l - q0_l (FP64, built by k_acf_tables).
+__global__ __launch_bounds__(NTHR) void k_acf_tables(GaussArgs a, double2* tab) {
+  const PacketGeom& G = *a.geom;
+  for (int l = 0; l < G.D; ++l) {
+    const AxisDesc& ax = G.ax[l];
+    const double lg = -0.25 * log(M_PI * a.sigma[l] * a.sigma[l]) + 0.5 * log(ax.dq);
+    for (int j = threadIdx.x; j < ax.n; j += NTHR) {
+      const double x = a.st->q_c[l] + (double)(j - ax.n / 2) * ax.dq - a.q0[l];
+      const double amp = exp(lg - x * x / (2.0 * a.sigma[l] * a.sigma[l]));
+      double sn, cs;
+      sincos(a.p0[l] * x / G.hbar, &sn, &cs);
+      tab[ax.tab_off + j] = double2{amp * cs, amp * sn};
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NTHR) void k_acf(const PacketGeom* geom, const typename CT<T>::type* psi,
+                                              const double2* tab, double* partials) {
+  const PacketGeom& G = *geom;
+  const int D = G.D;
+  double acc[MGK_NACC];
+#pragma unroll
+  for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
+  for (uint64_t e = (uint64_t)blockIdx.x * NTHR + threadIdx.x; e < G.N_total; e += (uint64_t)gridDim.x * NTHR) {
+    int j[MGK_MAXD];
+    decode_index(G, D, D, (uint32_t)e, 0, 0, j);
+    double2 f = tab[G.ax[0].tab_off + j[0]];
+    for (int l = 1; l < D; ++l) {
+      const double2 g = tab[G.ax[l].tab_off + j[l]];
+      f = double2{f.x * g.x - f.y * g.y, f.x * g.y + f.y * g.x};
+    }
+    const auto x = psi[G.off + e];
+    // conj(f) * x
+    acc[0] += f.x * (double)x.x + f.y * (double)x.y;
+    acc[1] += f.x * (double)x.y - f.y * (double)x.x;
+  }
+  __shared__ double red[(NTHR / 64) * MGK_NACC];
+  block_reduce<NTHR>(acc, D + 2, partials + (size_t)blockIdx.x * MGK_NACC, red);
+}
+
 // ===========================================================================
 // Host runtime
 // ===========================================================================
@@ -494,6 +538,7 @@ struct mg_ctx {
   int split = MG_TVT;
   std::vector<double> gam{1.0};
   int opt_graph = 0, opt_profile = 0, opt_renorm = 0, opt_engine = 0;
+  double2* d_acf = nullptr;  // per-axis factors of the autocorrelation reference (sum N_l)
   int grid_mode = 0;  // MG_OPT_GRID: 0 moving (Sec. II.G), 1 fixed, 2 naive re-centring (Sec. II.F)
   std::vector<ProfEntry> prof_pending;
   std::map<int, std::pair<int64_t, double>> prof;  // class -> (launches, ms)
@@ -1008,6 +1053,7 @@ void mg_destroy(mg_ctx* c) {
   hipFree(c->d_part);
   if (c->d_AG) hipFree(c->d_AG);
   if (c->d_MG) hipFree(c->d_MG);
+  if (c->d_acf) (void)hipFree(c->d_acf);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->gcap) (void)hipStreamDestroy(c->gcap);
   delete c;
@@ -1209,6 +1255,61 @@ mg_status mg_observables(mg_ctx* c, double* out) {
   out[1 + 4 * D] = sp[D + 1] / sp[0];
   out[2 + 4 * D] = sq[D + 1] / sq[0];
   out[3 + 4 * D] = st.t;
+  return MG_OK;
+}
+
+mg_status mg_autocorrelation(mg_ctx* c, const double* q0, const double* p0, const double* sigma, double* out) {
+  if (!c || !q0 || !p0 || !sigma || !out) return MG_EINVAL;
+  if (!c->has_state) return fail(c, MG_ESTATE, "no valid state");
+  GaussArgs a;
+  memset(&a, 0, sizeof(a));
+  a.geom = c->d_geom;
+  a.st = c->d_st;
+  for (int l = 0; l < c->D; ++l) {
+    if (!(sigma[l] > 0.0) || !std::isfinite(q0[l]) || !std::isfinite(p0[l]))
+      return fail(c, MG_EINVAL, "bad Gaussian parameters");
+    a.q0[l] = q0[l];
+    a.p0[l] = p0[l];
+    a.sigma[l] = sigma[l];
+  }
+  if (!c->d_acf) HIPCHK(c, hipMalloc(&c->d_acf, sizeof(double2) * (size_t)c->geom.tab_len));
+  hipLaunchKernelGGL(k_acf_tables, dim3(1), dim3(NTHR), 0, c->stream, a, c->d_acf);
+  HIPCHK(c, hipGetLastError());
+  const int grid = grid_for((c->geom.N_total + NTHR - 1) / NTHR);
+  if (c->prec == MG_C64) {
+    hipLaunchKernelGGL(k_acf<float>, dim3(grid), dim3(NTHR), 0, c->stream, c->d_geom, (const float2*)c->psi,
+                       (const double2*)c->d_acf, c->d_part);
+  } else {
+    hipLaunchKernelGGL(k_acf<double>, dim3(grid), dim3(NTHR), 0, c->stream, c->d_geom, (const double2*)c->psi,
+                       (const double2*)c->d_acf, c->d_part);
+  }
+  HIPCHK(c, hipGetLastError());
+  mg_status r = c->prec == MG_C64 ? launch_finalize<float>(c, FIN_OBSQ, 0.0, grid, nullptr)
+                                  : launch_finalize<double>(c, FIN_OBSQ, 0.0, grid, nullptr);
+  if (r) return r;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  PacketState st;
+  HIPCHK(c, hipMemcpy(&st, c->d_st, sizeof(st), hipMemcpyDeviceToHost));
+  out[0] = st.obs[0];
+  out[1] = st.obs[1];
+  return MG_OK;
+}
+
+mg_status mg_spectrum(const double* times, const double* acf, int n, const double* energies, int ne,
+                      double t_damp, double hbar, double* out) {
+  if (!times || !acf || !energies || !out || n < 2 || ne < 0 || !(t_damp > 0.0) || !(hbar > 0.0))
+    return MG_EINVAL;
+  for (int k = 0; k < ne; ++k) {
+    double s = 0.0, prev = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double t = times[i], f = exp(-(t / t_damp) * (t / t_damp));
+      const double ph = energies[k] * t / hbar;
+      const double v = f * (acf[2 * i] * cos(ph) - acf[2 * i + 1] * sin(ph));  // Re[acf e^{i E t}]
+      if (i > 0) s += 0.5 * (t - times[i - 1]) * (v + prev);
+      prev = v;
+    }
+    out[k] = s;
+  }
   return MG_OK;
 }
 

@@ -71,3 +71,19 @@ def test_null_context_calls_fail_cleanly(lib):
     assert lib.mg_observables(None, None) == _lib.MG_EINVAL
     assert lib.mg_state_bytes(None) == 0
     assert isinstance(lib.mg_last_error(None), bytes)
+
+
+def test_spectrum_host_function_matches_oracle():
+    """mg_spectrum is host arithmetic (no device work): it must equal the oracle's
+    trapezoidal transform of the same autocorrelation series."""
+    import numpy as np
+    import oracle as O
+    import paper_1909_06412_amd as mg
+    t = np.linspace(0.0, 40.0, 801)
+    acf = np.exp(-1j * 1.3 * t) * np.exp(-0.01 * t) + 0.3 * np.exp(-1j * 2.7 * t)
+    E = np.linspace(0.0, 4.0, 57)
+    got = mg.spectrum(t, acf, E, t_damp=30.0)
+    ref = O.spectrum(t, acf, E, t_damp=30.0)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # peaks at the two frequencies of the synthetic series
+    assert abs(E[np.argmax(got)] - 1.3) < 0.08
