@@ -197,6 +197,52 @@ __device__ __forceinline__ void line_model(int L, const int* jfix, double M0, do
   cp[3] = b2L * (1.0 / 3.0) * d * d * d;
 }
 
+// Henon-Heiles (Sec. III.C) on a contiguous tile, which holds the innermost three
+// axes L, L+1, L+2 (= D-3..D-1): every term of V and of dV/dq_m that involves only
+// the outer axes is the same for the whole tile and comes from LDS (tcs: per outer
+// axis m its share of V, its gradient component without the x-dependent pair
+// (L-1, L), and q_{L-1}); the line along axis L adds the terms of its own axes.
+// Same quantities as line_model: the weight moments' gradient sums into acc and the
+// cubic V(s), s = k - 8.
+__device__ __forceinline__ void line_model_hh_tile(int L, int D, int j1, int j2, double M0, double M1, double M2,
+                                                   const LineCst& lc, const double* tcs, double* acc, double* cp) {
+  const double ka = lc.pot.p[0], la = lc.pot.p[1];
+  const double d = lc.dq[L];
+  const double xc = lc.qc[L];
+  const double y = lc.qc[L + 1] + (double)(j1 - 8) * lc.dq[L + 1];
+  const double z = lc.qc[L + 2] + (double)(j2 - 8) * lc.dq[L + 2];
+  const bool hasm = L >= 1;
+  const double qm = hasm ? tcs[2 * MGK_MAXD] : 0.0;
+  double tout = 0.0;
+#pragma unroll
+  for (int m = 0; m < MGK_MAXD; ++m)
+    if (m < L) tout += tcs[m];
+  const double S1 = d * M1, S2 = d * d * M2;
+  const double V0 = tout + (hasm ? la * (qm * qm * xc - xc * xc * xc * (1.0 / 3.0)) : 0.0) +
+                    0.5 * ka * (xc * xc + y * y + z * z) + la * (xc * xc * y - y * y * y * (1.0 / 3.0)) +
+                    la * (y * y * z - z * z * z * (1.0 / 3.0));
+  const double gL = ka * xc + (hasm ? la * (qm * qm - xc * xc) : 0.0) + 2.0 * la * xc * y;
+  const double gL1 = ka * y + la * (xc * xc - y * y) + 2.0 * la * y * z;
+  const double gL2 = ka * z + la * (y * y - z * z);
+  const double b1L = ka + 2.0 * la * y - (hasm ? 2.0 * la * xc : 0.0);
+  const double b2L = hasm ? -la : 0.0;
+#pragma unroll
+  for (int m = 0; m < MGK_MAXD; ++m) {
+    if (m >= D) continue;
+    double v;
+    if (m < L - 1) v = tcs[MGK_MAXD + m] * M0;
+    else if (m == L - 1) v = (tcs[MGK_MAXD + m] + 2.0 * la * qm * xc) * M0 + 2.0 * la * qm * S1;
+    else if (m == L) v = gL * M0 + b1L * S1 + b2L * S2;
+    else if (m == L + 1) v = gL1 * M0 + 2.0 * la * xc * S1 + la * S2;
+    else v = gL2 * M0;
+    acc[1 + m] += v;
+  }
+  cp[0] = V0;
+  cp[1] = gL * d;
+  cp[2] = 0.5 * b1L * d * d;
+  cp[3] = b2L * (1.0 / 3.0) * d * d * d;
+}
+
 // Epilogue on a line held in registers (strided tiles): moments (REDP) or the
 // potential substep (V) with weights w_k = |x_k|^2.
 template <typename T, int EPI, int PK>
@@ -269,6 +315,7 @@ void k_sweep16(S16Args<T> a) {
   const C* __restrict__ AG = a.AG + d.gtab_off;
   const C* __restrict__ MG = a.MG + d.gtab_off;
   __shared__ LineCst lc;
+  __shared__ double tcs[2 * MGK_MAXD + 1];  // per-tile outer-axis terms (Henon-Heiles, contiguous tiles)
   if (EPI == EPI_V) stage_line_cst(lc, G, *a.st, *a.pot);
   // Strided tiles keep the sweep's group tables (16^K entries) in LDS for the
   // whole launch; the table index of a thread's points is the same in every tile.
@@ -389,6 +436,28 @@ void k_sweep16(S16Args<T> a) {
       // thread t then owns positions t + 256 m, a line along the outermost group
       // axis (packet axis a), and streams it: pass 1 reduces, pass 2 applies the
       // phase and the conj(A) factor and stores 512 contiguous bytes per wave.
+      if constexpr (EPI == EPI_V && PK == 3) {
+        // Henon-Heiles terms of the outer axes of this tile (one thread per axis)
+        const int L = d.a;
+        if (t < (uint32_t)L) {
+          const double ka = lc.pot.p[0], la = lc.pot.p[1];
+          auto qo = [&](int l) {
+            return lc.qc[l] + (double)((int)((flat0 >> (4 * (D - 1 - l))) & 15u) - 8) * lc.dq[l];
+          };
+          const int m = (int)t;
+          const double qv = qo(m);
+          double term = 0.5 * ka * qv * qv, g = ka * qv;
+          if (m >= 1) {
+            const double qp = qo(m - 1);
+            term += la * (qp * qp * qv - qv * qv * qv * (1.0 / 3.0));
+            g += la * (qp * qp - qv * qv);
+          }
+          if (m + 1 <= L - 1) g += 2.0 * la * qv * qo(m + 1);
+          tcs[m] = term;
+          tcs[MGK_MAXD + m] = g;
+          if (m == L - 1) tcs[2 * MGK_MAXD] = qv;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
       __syncthreads();
@@ -417,7 +486,10 @@ void k_sweep16(S16Args<T> a) {
             if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
         }
         if (EPI == EPI_V) {
-          line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, cp);
+          if constexpr (PK == 3)
+            line_model_hh_tile(L, D, (int)((t >> 4) & 15u), (int)(t & 15u), wl, ml, m2, lc, tcs, acc, cp);
+          else
+            line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, cp);
 #pragma unroll
           for (int i = 0; i < 4; ++i) cp[i] *= hh;
           if (INV) {

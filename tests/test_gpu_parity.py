@@ -249,3 +249,20 @@ def test_sixteen_point_duschinsky_table_model():
     """The paper's 3-D Duschinsky model (full K, unequal masses) on a 16^3 grid."""
     w = W.duschinsky_3d(n=16, dq=0.6)
     compare(w, 2, "c128", TOL128)
+
+
+def test_secrest_johnson_model_tenth_order_vtv():
+    """The paper's modified Secrest-Johnson collinear model (Sec. III.B): Morse
+    diatom + exponential repulsion on the atom-diatom distance, unequal masses,
+    10th-order triple-jump VTV composition; state, centres and energies."""
+    w = W.secrest_johnson_2d()
+    n = 3
+    e = compare(w, n, "c128", TOL128)
+    wp, pot = oracle_run(w, n)
+    m = gpu_run(w, n, "c128")
+    ob = m.observables()
+    m.close()
+    oo = O.observables(wp, pot, w["inv_mass"])
+    print(f"[parity] secrest-johnson: E_gpu {ob['Ekin'] + ob['Epot']:.15f} E_oracle {oo['E']:.15f}", flush=True)
+    assert abs(ob["Ekin"] + ob["Epot"] - oo["E"]) < 1e-11 * abs(oo["E"])
+    assert e < TOL128
