@@ -223,7 +223,9 @@ __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double
   double V = 0.0;
   switch (PK >= 0 ? PK : P.kind) {
     case 1: {  // harmonic: k[D], s[D]
-      for (int l = 0; l < D; ++l) {
+#pragma unroll
+      for (int l = 0; l < MGK_MAXD; ++l) {
+        if (l >= D) break;
         const double x = q[l] - P.p[D + l];
         V += 0.5 * P.p[l] * x * x;
         if (g) g[l] = P.p[l] * x;
@@ -245,11 +247,15 @@ __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double
     }
     case 3: {  // Henon-Heiles: kappa, lam
       const double ka = P.p[0], la = P.p[1];
-      for (int l = 0; l < D; ++l) {
+#pragma unroll
+      for (int l = 0; l < MGK_MAXD; ++l) {
+        if (l >= D) break;
         V += 0.5 * ka * q[l] * q[l];
         if (g) g[l] = ka * q[l];
       }
-      for (int l = 0; l + 1 < D; ++l) {
+#pragma unroll
+      for (int l = 0; l + 1 < MGK_MAXD; ++l) {
+        if (l + 1 >= D) break;
         const double a = q[l], b = q[l + 1];
         V += la * (a * a * b - b * b * b / 3.0);
         if (g) {
@@ -261,18 +267,26 @@ __device__ __forceinline__ double pot_eval(const PotDesc& P, int D, const double
     }
     case 4: {  // quadratic: K[D*D], s[D]  (D <= 4)
       double x[4];
-      for (int l = 0; l < D; ++l) x[l] = q[l] - P.p[D * D + l];
-      for (int a = 0; a < D; ++a) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) x[l] = l < D ? q[l] - P.p[D * D + l] : 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (a >= D) break;
         double row = 0.0;
-        for (int b = 0; b < D; ++b) row += P.p[a * D + b] * x[b];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (b < D) row += P.p[a * D + b] * x[b];
         V += 0.5 * x[a] * row;
         if (g) g[a] = row;
       }
       break;
     }
     default:
-      if (g)
-        for (int l = 0; l < D; ++l) g[l] = 0.0;
+      if (g) {
+#pragma unroll
+        for (int l = 0; l < MGK_MAXD; ++l)
+          if (l < D) g[l] = 0.0;
+      }
       break;
   }
   return V;
@@ -425,7 +439,9 @@ template <int NTHR>
 __device__ __forceinline__ void block_reduce(double* acc, int nacc, double* out, double* red) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
-  for (int k = 0; k < nacc; ++k) {
+#pragma unroll
+  for (int k = 0; k < MGK_NACC; ++k) {
+    if (k >= nacc) break;
     double v = acc[k];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -444,21 +460,18 @@ __device__ __forceinline__ void block_reduce(double* acc, int nacc, double* out,
 // Decode the multi-index of a point from (outer, group, inner) parts of a sweep.
 __device__ __forceinline__ void decode_index(const PacketGeom& G, int a, int b, uint32_t o, uint32_t g,
                                              uint32_t i, int* j) {
+  // unrolled over MGK_MAXD so that j[] (and the caller's per-axis arrays) keep
+  // static indices and live in registers
   const int D = G.D;
-  for (int l = D - 1; l >= b; --l) {
-    const uint32_t qq = divw(i, G.ax[l].dn);
-    j[l] = (int)(i - qq * (uint32_t)G.ax[l].n);
-    i = qq;
-  }
-  for (int l = b - 1; l >= a; --l) {
-    const uint32_t qq = divw(g, G.ax[l].dn);
-    j[l] = (int)(g - qq * (uint32_t)G.ax[l].n);
-    g = qq;
-  }
-  for (int l = a - 1; l >= 0; --l) {
-    const uint32_t qq = divw(o, G.ax[l].dn);
-    j[l] = (int)(o - qq * (uint32_t)G.ax[l].n);
-    o = qq;
+#pragma unroll
+  for (int l = MGK_MAXD - 1; l >= 0; --l) {
+    if (l >= D) continue;
+    const uint32_t v = l >= b ? i : (l >= a ? g : o);
+    const uint32_t qq = divw(v, G.ax[l].dn);
+    j[l] = (int)(v - qq * (uint32_t)G.ax[l].n);
+    if (l >= b) i = qq;
+    else if (l >= a) g = qq;
+    else o = qq;
   }
 }
 
@@ -486,27 +499,41 @@ __device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::t
   const double w = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
   if (mode & (EPI_REDP | EPI_REDQ)) {
     acc[0] += w;
-    for (int l = 0; l < D; ++l) acc[1 + l] += w * (double)(j[l] - G.ax[l].n / 2);
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l)
+      if (l < D) acc[1 + l] += w * (double)(j[l] - G.ax[l].n / 2);
     if (mode & EPI_EKIN) {
       double e = 0.0;
-      for (int l = 0; l < D; ++l) {
+#pragma unroll
+      for (int l = 0; l < MGK_MAXD; ++l) {
+        if (l >= D) break;
         const double p = st.p_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dp;
         e += 0.5 * G.ax[l].minv * p * p;
       }
-      acc[D + 1] += w * e;
+      // slot D + 1 by select-adds over fixed indices: a dynamic index would put the
+      // whole accumulator array in scratch memory for every epilogue of the kernel
+      const double we = w * e;
+#pragma unroll
+      for (int k = 2; k < MGK_NACC; ++k) acc[k] += (k == D + 1) ? we : 0.0;
     }
     if (mode & EPI_REDQ) {
       double q[MGK_MAXD];
-      for (int l = 0; l < D; ++l) q[l] = st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq;
-      acc[D + 1] += w * pot_eval(P, D, q, nullptr);
+#pragma unroll
+      for (int l = 0; l < MGK_MAXD; ++l) q[l] = l < D ? st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq : 0.0;
+      const double Vq = w * pot_eval(P, D, q, nullptr);
+#pragma unroll
+      for (int k = 2; k < MGK_NACC; ++k) acc[k] += (k == D + 1) ? Vq : 0.0;
     }
   }
   if (mode & EPI_V) {
     double q[MGK_MAXD], g[MGK_MAXD];
-    for (int l = 0; l < D; ++l) q[l] = st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq;
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l) q[l] = l < D ? st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq : 0.0;
     const double V = pot_eval(P, D, q, g);
     acc[0] += w;
-    for (int l = 0; l < D; ++l) acc[1 + l] += w * g[l];
+#pragma unroll
+    for (int l = 0; l < MGK_MAXD; ++l)
+      if (l < D) acc[1 + l] += w * g[l];
     x = cmul(x, phase_of<T>(h * V / G.hbar));
   }
   return x;
