@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -78,9 +79,9 @@ __global__ __launch_bounds__(NTHR) void k_pointwise(PointArgs<T> a) {
   for (uint64_t e = (uint64_t)blockIdx.x * NTHR + threadIdx.x; e < N; e += (uint64_t)gridDim.x * NTHR) {
     int j[MGK_MAXD];
     decode_index(G, G.D, G.D, (uint32_t)e, 0, 0, j);
-    C x = a.psi[G.off + e];
+    C x = gload(a.psi, G.off + e);
     x = epilogue_point<T>(x, j, G, *a.st, *a.pot, a.epi, a.h, acc);
-    if (a.epi & (EPI_V | EPI_SCALE)) a.psi[G.off + e] = x;
+    if (a.epi & (EPI_V | EPI_SCALE)) gstore(a.psi, G.off + e, x);
   }
   __shared__ double red[(NTHR / 64) * MGK_NACC];
   if (a.epi & (EPI_V | EPI_REDQ | EPI_REDP))
@@ -305,10 +306,46 @@ std::vector<int> radices(int n) {
   return r;
 }
 
+// Passes for the ping-pong pass, which also has the composite radices 9, 10, 12,
+// 15 and 16: fewest passes, then the smallest largest radix (fewer registers per
+// butterfly), larger radices first.
+static bool wide_better(const std::vector<int>& a, const std::vector<int>& b) {
+  if (a.size() != b.size()) return a.size() < b.size();
+  const int ma = *std::max_element(a.begin(), a.end()), mb = *std::max_element(b.begin(), b.end());
+  if (ma != mb) return ma < mb;
+  return std::lexicographical_compare(b.begin(), b.end(), a.begin(), a.end());
+}
+std::vector<int> radices_wide(int n) {
+  static const int kR[] = {16, 15, 12, 10, 9, 8, 5, 4, 3, 2};
+  std::map<int, std::vector<int>> best;  // m | n -> plan for m
+  best[1] = {};
+  std::vector<int> divs;
+  for (int m = 2; m <= n; ++m)
+    if (n % m == 0) divs.push_back(m);
+  for (int m : divs) {  // increasing: every proper divisor of m is already planned
+    bool have = false;
+    std::vector<int> pick;
+    for (int r : kR) {
+      if (m % r) continue;
+      auto it = best.find(m / r);
+      if (it == best.end()) continue;
+      std::vector<int> c = it->second;
+      c.push_back(r);
+      std::sort(c.begin(), c.end(), std::greater<int>());
+      if (!have || wide_better(c, pick)) {
+        pick = c;
+        have = true;
+      }
+    }
+    if (have) best[m] = pick;
+  }
+  return best.count(n) ? best[n] : radices(n);
+}
+
 // Build the per-axis passes and the sweep plan of one packet.
 bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, double hbar, int tw_base,
                 std::map<int, int>& tw_offsets, int& tw_total, PacketGeom& G, std::string& err,
-                uint32_t tmax = MGK_TMAX) {
+                uint32_t tmax = MGK_TMAX, bool wide = false) {
   memset(&G, 0, sizeof(G));
   G.D = D;
   G.hbar = hbar;
@@ -340,7 +377,7 @@ bool build_geom(int D, const int32_t* N, const double* dq, const double* minv, d
     } else {
       ax.tw_off = it->second;
     }
-    std::vector<int> rs = radices(n);
+    std::vector<int> rs = wide ? radices_wide(n) : radices(n);
     ax.npass = (int)rs.size();
     int Ns = 1;
     for (size_t p = 0; p < rs.size(); ++p) {

@@ -29,6 +29,32 @@ template <typename T> struct CT;
 template <> struct CT<float> { typedef float2 type; };
 template <> struct CT<double> { typedef double2 type; };
 
+// Loads and stores of the wavepacket state through global-address-space pointers.
+// The state always lives in device memory; saying so lets the compiler keep the
+// LDS-staged plan, state and potential in registers across loops that store the
+// state (a generic store might alias LDS, so every descriptor field would be
+// re-read, one LDS round trip each, per element), and emit global rather than flat
+// memory instructions.
+// (The host pass only parses these; address spaces exist in the device pass.)
+template <typename C> __device__ __forceinline__ C gload(const C* p, uint64_t i) {
+#ifdef __HIP_DEVICE_COMPILE__
+  typedef __attribute__((address_space(1))) const C GC;
+  C r;
+  __builtin_memcpy(&r, (const void*)((const GC*)p + i), sizeof(C));
+  return r;
+#else
+  return p[i];
+#endif
+}
+template <typename C> __device__ __forceinline__ void gstore(C* p, uint64_t i, C v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  typedef __attribute__((address_space(1))) C GC;
+  ((GC*)p)[i] = v;
+#else
+  p[i] = v;
+#endif
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {
@@ -117,12 +143,78 @@ template <typename T, typename C> __device__ __forceinline__ void dft5(C* v, boo
   v[3] = csub(m2, n2);
 }
 
+// Roots of unity of the composite radices (exact where the angle is a multiple of
+// pi/2, pi/4 or pi/6; otherwise the double nearest the reduced-angle value).
+template <int R> struct Unity;
+template <> struct Unity<9> {
+  static constexpr double c[9] = {1.0, 0.766044443118978, 0.17364817766693033, -0.5, -0.9396926207859084, -0.9396926207859084, -0.5, 0.17364817766693033, 0.766044443118978};
+  static constexpr double s[9] = {0.0, 0.6427876096865393, 0.984807753012208, 0.8660254037844386, 0.3420201433256687, -0.3420201433256687, -0.8660254037844386, -0.984807753012208, -0.6427876096865393};
+};
+template <> struct Unity<10> {
+  static constexpr double c[10] = {1.0, 0.8090169943749475, 0.3090169943749474, -0.3090169943749474, -0.8090169943749475, -1.0, -0.8090169943749475, -0.3090169943749474, 0.3090169943749474, 0.8090169943749475};
+  static constexpr double s[10] = {0.0, 0.5877852522924731, 0.9510565162951535, 0.9510565162951535, 0.5877852522924731, 0.0, -0.5877852522924731, -0.9510565162951535, -0.9510565162951535, -0.5877852522924731};
+};
+template <> struct Unity<12> {
+  static constexpr double c[12] = {1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5, 0.0, 0.5, 0.8660254037844386};
+  static constexpr double s[12] = {0.0, 0.5, 0.8660254037844386, 1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5};
+};
+template <> struct Unity<15> {
+  static constexpr double c[15] = {1.0, 0.9135454576426009, 0.6691306063588582, 0.3090169943749474, -0.10452846326765346, -0.5, -0.8090169943749475, -0.9781476007338057, -0.9781476007338057, -0.8090169943749475, -0.5, -0.10452846326765346, 0.3090169943749474, 0.6691306063588582, 0.9135454576426009};
+  static constexpr double s[15] = {0.0, 0.40673664307580015, 0.7431448254773942, 0.9510565162951535, 0.9945218953682733, 0.8660254037844386, 0.5877852522924731, 0.20791169081775931, -0.20791169081775931, -0.5877852522924731, -0.8660254037844386, -0.9945218953682733, -0.9510565162951535, -0.7431448254773942, -0.40673664307580015};
+};
+template <> struct Unity<16> {
+  static constexpr double c[16] = {1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898, 0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867};
+  static constexpr double s[16] = {0.0, 0.3826834323650898, 0.7071067811865476, 0.9238795325112867, 1.0, 0.9238795325112867, 0.7071067811865476, 0.3826834323650898, 0.0, -0.3826834323650898, -0.7071067811865476, -0.9238795325112867, -1.0, -0.9238795325112867, -0.7071067811865476, -0.3826834323650898};
+};
+
+template <typename T, int R, typename C> __device__ __forceinline__ void dftR(C* v, bool inv);
+
+// Composite radix R = A B in registers (Cooley-Tukey inside the butterfly):
+// input n = B a + b, output k = k1 + A k2; A-point DFTs over a for each b,
+// multiplication by w_R^(b k1), then B-point DFTs over b for each k1.
+template <typename T, int A, int B, typename C> __device__ __forceinline__ void dft_ab(C* v, bool inv) {
+  constexpr int R = A * B;
+  C t[R];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    C u[A];
+#pragma unroll
+    for (int a = 0; a < A; ++a) u[a] = v[B * a + b];
+    dftR<T, A>(u, inv);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      C x = u[k1];
+      const int m = (b * k1) % R;
+      if (m != 0) {
+        const T c = (T)Unity<R>::c[m], sn = (T)Unity<R>::s[m];
+        // forward w = c - i sn, inverse w = c + i sn
+        x = inv ? C{x.x * c - x.y * sn, x.x * sn + x.y * c} : C{x.x * c + x.y * sn, x.y * c - x.x * sn};
+      }
+      t[b * A + k1] = x;
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) {
+    C u[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) u[b] = t[b * A + k1];
+    dftR<T, B>(u, inv);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = u[k2];
+  }
+}
+
 template <typename T, int R, typename C> __device__ __forceinline__ void dftR(C* v, bool inv) {
   if constexpr (R == 2) dft2(v);
   else if constexpr (R == 3) dft3<T>(v, inv);
   else if constexpr (R == 4) dft4(v, inv);
   else if constexpr (R == 5) dft5<T>(v, inv);
   else if constexpr (R == 8) dft8<T>(v, inv);
+  else if constexpr (R == 9) dft_ab<T, 3, 3>(v, inv);
+  else if constexpr (R == 10) dft_ab<T, 2, 5>(v, inv);
+  else if constexpr (R == 12) dft_ab<T, 4, 3>(v, inv);
+  else if constexpr (R == 15) dft_ab<T, 3, 5>(v, inv);
+  else if constexpr (R == 16) dft_ab<T, 4, 4>(v, inv);
 }
 
 // ---------------------------------------------------------------------------
@@ -189,6 +281,84 @@ __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_
     }
   }
   __syncthreads();
+}
+
+// The same pass out of place (Stockham ping-pong between two LDS buffers): each
+// butterfly reads from `in` and writes to `out` at once, so a thread holds only
+// its R values and a pass needs one barrier, at the price of a second tile of LDS.
+template <typename T, int R, int NTHR>
+__device__ __forceinline__ void stockham_pass_pp(const typename CT<T>::type* __restrict__ in,
+                                                 typename CT<T>::type* __restrict__ out, uint32_t Tn, uint32_t n,
+                                                 uint32_t S, Div32 dS, const PassDesc& pd, bool inv,
+                                                 const typename CT<T>::type* __restrict__ tw,
+                                                 const typename CT<T>::type* __restrict__ pre,
+                                                 const typename CT<T>::type* __restrict__ post, bool post_conj) {
+  typedef typename CT<T>::type C;
+  const uint32_t nbl = n / R;
+  const uint32_t nb = Tn / R;
+  const uint32_t Ns = pd.Ns;
+  for (uint32_t bf = threadIdx.x; bf < nb; bf += NTHR) {
+    uint32_t b0, j;
+    bfly_index(bf, n, S, dS, pd.dNbl, &b0, &j);
+    C v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = in[b0 + (j + r * nbl) * S];
+    if (pre) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = cmul(v[r], pre[j + r * nbl]);
+    }
+    const uint32_t k = j - div32(j, pd.dNs) * Ns;
+    if (Ns > 1) {
+      const uint32_t step = k * pd.tws;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        C w = tw[r * step];
+        v[r] = inv ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    dftR<T, R>(v, inv);
+    const uint32_t o0 = (j - k) * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint32_t p = o0 + r * Ns;
+      C x = v[r];
+      if (post) x = post_conj ? cmulc(x, post[p]) : cmul(x, post[p]);
+      out[b0 + p * S] = x;
+    }
+  }
+  __syncthreads();
+}
+
+// All passes of axis `ax` with the ping-pong pass; *cur selects the buffer that
+// holds the data (0: a, 1: b) on entry and on return.  Besides 2, 3, 4, 5 and 8
+// this pass takes the composite radices 9, 10, 12, 15 and 16 (plans made with
+// wide radices), so most 5-smooth lengths up to 256 need two passes.
+template <typename T, int NTHR>
+__device__ __forceinline__ void tile_axis_fft_pp(typename CT<T>::type* a, typename CT<T>::type* b, int* cur,
+                                                 uint32_t Tn, const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
+                                                 const typename CT<T>::type* tw, const typename CT<T>::type* pre,
+                                                 const typename CT<T>::type* post, bool post_conj) {
+  const int np = ax.npass;
+  for (int p = 0; p < np; ++p) {
+    const PassDesc& pd = ax.pass[p];
+    const typename CT<T>::type* pr = p == 0 ? pre : nullptr;
+    const typename CT<T>::type* po = p == np - 1 ? post : nullptr;
+    typename CT<T>::type* src = *cur ? b : a;
+    typename CT<T>::type* dst = *cur ? a : b;
+    switch (pd.R) {
+      case 2: stockham_pass_pp<T, 2, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 3: stockham_pass_pp<T, 3, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 4: stockham_pass_pp<T, 4, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 5: stockham_pass_pp<T, 5, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 9: stockham_pass_pp<T, 9, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 10: stockham_pass_pp<T, 10, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 12: stockham_pass_pp<T, 12, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 15: stockham_pass_pp<T, 15, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 16: stockham_pass_pp<T, 16, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      default: stockham_pass_pp<T, 8, NTHR>(src, dst, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+    }
+    *cur ^= 1;
+  }
 }
 
 // FFT of every line of axis `ax` in the tile (all passes of that axis).
@@ -457,22 +627,41 @@ __device__ __forceinline__ void block_reduce(double* acc, int nacc, double* out,
   __syncthreads();
 }
 
+// Per-axis index-decode constants read once into registers before an element
+// loop (read inside it, each would cost an LDS or memory round trip per element).
+struct AxDec {
+  uint32_t n[MGK_MAXD];
+  DivW dn[MGK_MAXD];
+};
+__device__ __forceinline__ AxDec load_axdec(const PacketGeom& G, int D) {
+  AxDec A;
+#pragma unroll
+  for (int l = 0; l < MGK_MAXD; ++l) {
+    A.n[l] = l < D ? (uint32_t)G.ax[l].n : 1u;
+    A.dn[l] = l < D ? G.ax[l].dn : DivW{1u, 0u, 0ull};
+  }
+  return A;
+}
+
 // Decode the multi-index of a point from (outer, group, inner) parts of a sweep.
-__device__ __forceinline__ void decode_index(const PacketGeom& G, int a, int b, uint32_t o, uint32_t g,
+__device__ __forceinline__ void decode_index(const AxDec& A, int D, int a, int b, uint32_t o, uint32_t g,
                                              uint32_t i, int* j) {
   // unrolled over MGK_MAXD so that j[] (and the caller's per-axis arrays) keep
   // static indices and live in registers
-  const int D = G.D;
 #pragma unroll
   for (int l = MGK_MAXD - 1; l >= 0; --l) {
     if (l >= D) continue;
     const uint32_t v = l >= b ? i : (l >= a ? g : o);
-    const uint32_t qq = divw(v, G.ax[l].dn);
-    j[l] = (int)(v - qq * (uint32_t)G.ax[l].n);
+    const uint32_t qq = divw(v, A.dn[l]);
+    j[l] = (int)(v - qq * A.n[l]);
     if (l >= b) i = qq;
     else if (l >= a) g = qq;
     else o = qq;
   }
+}
+__device__ __forceinline__ void decode_index(const PacketGeom& G, int a, int b, uint32_t o, uint32_t g,
+                                             uint32_t i, int* j) {
+  decode_index(load_axdec(G, G.D), G.D, a, b, o, g, i, j);
 }
 
 // Epilogue modes of a sweep / pointwise pass (bit flags).
@@ -485,12 +674,13 @@ enum : int {
 };
 
 // Pointwise work on one element with full multi-index j; returns the new value.
-template <typename T>
+// DT > 0 fixes the number of axes at compile time (specialised batch kernels).
+template <typename T, int DT = 0>
 __device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::type x, const int* j,
                                                                const PacketGeom& G, const PacketState& st,
                                                                const PotDesc& P, int mode, double h,
                                                                double* acc) {
-  const int D = G.D;
+  const int D = DT > 0 ? DT : G.D;
   if (mode & EPI_SCALE) {
     const T s = (T)st.scale;
     x.x *= s;

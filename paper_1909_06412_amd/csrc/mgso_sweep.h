@@ -43,8 +43,19 @@ __device__ __forceinline__ TileOrigin tile_origin(const PacketGeom& G, const Swe
   return t;
 }
 
+// In-tile decode constants of a sweep, read once into registers before the
+// element loops of a tile.
+struct TileDec {
+  int32_t kind;
+  uint32_t LG, r, I;
+  Div32 dLG, dr;
+};
+__device__ __forceinline__ TileDec tile_dec(const SweepDesc& sw) {
+  return TileDec{sw.kind, sw.LG, sw.r, sw.I, sw.dLG, sw.dr};
+}
+
 // Element t of the tile -> (global offset, valid, group index g, outer o, inner i)
-__device__ __forceinline__ bool tile_elem(const SweepDesc& sw, const TileOrigin& to, uint32_t t, uint64_t* gofs,
+__device__ __forceinline__ bool tile_elem(const TileDec& sw, const TileOrigin& to, uint32_t t, uint64_t* gofs,
                                           uint32_t* g, uint32_t* o, uint32_t* i) {
   if (sw.kind == 0) {
     const uint32_t row = div32(t, sw.dLG);
@@ -67,7 +78,9 @@ __device__ __forceinline__ bool tile_elem(const SweepDesc& sw, const TileOrigin&
 // Process one tile: load from src, transform the sweep's axes (forward with A pre-
 // multiplication, or inverse with M pre- and conj(A) post-multiplication), run the
 // pointwise epilogue and store to dst.  acc collects the epilogue's FP64 sums.
-template <typename T, int NTHR, int TM = MGK_TMAX>
+// PP: the transforms ping-pong between lds[0, TM) and lds[TM, 2 TM) (out-of-place
+// Stockham passes); the tile is back in lds[0, TM) after the epilogue.
+template <typename T, int NTHR, int TM = MGK_TMAX, bool PP = false, int DT = 0>
 __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const PacketGeom& G, int si, uint32_t tile,
                                              const typename CT<T>::type* src, typename CT<T>::type* dst,
                                              const Tables<T>& tb, int dir, int epi, double h,
@@ -77,38 +90,52 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
   const SweepDesc& sw = G.sw[si];
   const TileOrigin to = tile_origin(G, sw, tile);
   const uint32_t Tn = sw.T;
+  const TileDec td = tile_dec(sw);
   if (do_load) {
     for (uint32_t t = threadIdx.x; t < Tn; t += NTHR) {
       uint64_t gofs;
       uint32_t g, o, i;
-      const bool ok = tile_elem(sw, to, t, &gofs, &g, &o, &i);
-      lds[t] = ok ? src[gofs] : C{(T)0, (T)0};
+      const bool ok = tile_elem(td, to, t, &gofs, &g, &o, &i);
+      lds[t] = ok ? gload(src, gofs) : C{(T)0, (T)0};
     }
     __syncthreads();
   }
   const bool inv = dir == DIR_INV;
+  int cur = 0;
   for (int ai = 0; ai < sw.b - sw.a; ++ai) {
     const AxisDesc& ax = G.ax[sw.a + ai];
     const C* tw = tb.tw + ax.tw_off;
-    if (!inv) {
+    if constexpr (PP) {
+      if (!inv)
+        tile_axis_fft_pp<T, NTHR>(lds, lds + TM, &cur, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off,
+                                  nullptr, false);
+      else
+        tile_axis_fft_pp<T, NTHR>(lds, lds + TM, &cur, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
+                                  tb.A + ax.tab_off, true);
+    } else if (!inv) {
       tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off, nullptr, false);
     } else {
       tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
                              tb.A + ax.tab_off, true);
     }
   }
+  // after an odd number of ping-pong passes the tile sits in the second buffer;
+  // the epilogue reads it from there and writes each point back to lds[t]
+  const C* res = (PP && cur) ? lds + TM : lds;
+  const int D = DT > 0 ? DT : G.D, sa = sw.a, sb = sw.b;
+  const AxDec ad = load_axdec(G, D);
   for (uint32_t t = threadIdx.x; t < Tn; t += NTHR) {
     uint64_t gofs;
     uint32_t g, o, i;
-    const bool ok = tile_elem(sw, to, t, &gofs, &g, &o, &i);
+    const bool ok = tile_elem(td, to, t, &gofs, &g, &o, &i);
     if (!ok) continue;
-    C x = lds[t];
+    C x = res[t];
     if (epi) {
       int j[MGK_MAXD];
-      decode_index(G, sw.a, sw.b, o, g, i, j);
-      x = epilogue_point<T>(x, j, G, st, P, epi, h, acc);
+      decode_index(ad, D, sa, sb, o, g, i, j);
+      x = epilogue_point<T, DT>(x, j, G, st, P, epi, h, acc);
     }
-    if (do_store) dst[gofs] = x;
+    if (do_store) gstore(dst, gofs, x);
     else lds[t] = x;
   }
   __syncthreads();

@@ -87,3 +87,10 @@ def test_spectrum_host_function_matches_oracle():
     assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
     # peaks at the two frequencies of the synthetic series
     assert abs(E[np.argmax(got)] - 1.3) < 0.08
+
+
+def test_binding_knows_every_batch_launch_shape():
+    txt = open(HEADER).read()
+    n = int(re.search(r"#define MG_BATCH_CONFIGS (\d+)", txt).group(1))
+    import paper_1909_06412_amd as mg
+    assert mg.MovingGridBatch.N_CONFIGS == n

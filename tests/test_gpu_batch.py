@@ -130,3 +130,23 @@ def test_launch_shapes_and_autotune():
         print(f"[batch] shape {k} {b.config(k)}: worst packet error vs oracle {worst:.3e}", flush=True)
         assert worst < 2e-5
         b.close()
+
+
+def test_launch_shapes_c128():
+    """Every complex128 launch shape, in-place and ping-pong transforms alike,
+    matches the oracle packet by packet at the double-precision bar."""
+    mg = _mg()
+    ws = _batch_workloads(precision="c128")
+    nsteps = 10
+    refs = [oracle_packet(w, nsteps).physical() for w in ws]
+    for k in range(mg.MovingGridBatch.N_CONFIGS):
+        b = mg.batch_from_workloads(ws, precision="c128")
+        b.set_config(k)
+        b.step(ws[0]["dt"], nsteps)
+        worst = 0.0
+        for i, ref in enumerate(refs):
+            psi, *_ = b.get_state(i)
+            worst = max(worst, np.linalg.norm(psi - ref) / np.linalg.norm(ref))
+        print(f"[batch] c128 shape {k} {b.config(k)}: worst packet error vs oracle {worst:.3e}", flush=True)
+        assert worst < 1e-12
+        b.close()
