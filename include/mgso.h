@@ -260,9 +260,12 @@ mg_status mg_batch_set_option(mg_batch* b, int option, int64_t value);
  * A packet of at most `tile` points stays in LDS for a whole mg_batch_step call;
  * larger packets sweep through global memory tile by tile.  Shapes 3 and 4 run
  * the tile transforms out of place between two LDS buffers (a smaller tile, fewer
- * registers and barriers per pass, composite radices up to 16).  mg_batch_config reads pair `index` for the
+ * registers and barriers per pass, composite radices up to 16).  Shape 5 is not
+ * persistent: every sweep of every packet is one launch over 4096-point tiles and
+ * each moment reduction one launch with a workgroup per packet, so large packets
+ * spread over the whole device.  mg_batch_config reads pair `index` for the
  * batch's precision (MG_EINVAL out of range). */
-#define MG_BATCH_CONFIGS 5
+#define MG_BATCH_CONFIGS 6
 mg_status mg_batch_config(const mg_batch* b, int index, int* threads, int* tile);
 /* Use launch shape `index` for the following mg_batch_step calls (builds that
  * shape's per-packet plans on first use).  The batched adjoint keeps index 0. */

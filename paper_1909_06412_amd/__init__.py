@@ -252,7 +252,7 @@ class MovingGridBatch:
     def set_option(self, option, value):
         L.check(L.lib().mg_batch_set_option(self.h, int(option), int(value)), self.h)
 
-    N_CONFIGS = 5  # MG_BATCH_CONFIGS
+    N_CONFIGS = 6  # MG_BATCH_CONFIGS
 
     def config(self, index):
         """(threads per workgroup, tile points) of launch shape `index`."""

@@ -60,11 +60,16 @@ def test_step_graph_replays_match_eager(case, precision):
     b.close()
 
 
-def test_batch_graph_replays_match_eager():
+@pytest.mark.parametrize("shape", [0, 5])
+def test_batch_graph_replays_match_eager(shape):
+    """Persistent shape 0 (one captured launch) and the streaming shape 5 (a
+    captured sequence of sweep and update launches)."""
     mg = _mg()
     ws = W.morse_batch(B=12, precision="c64")
     a = mg.batch_from_workloads(ws, precision="c64")
     b = mg.batch_from_workloads(ws, precision="c64")
+    a.set_config(shape)
+    b.set_config(shape)
     b.set_option(mg.MG_OPT_GRAPH, 1)
     dt = ws[0]["dt"]
     for rep, (h, n) in enumerate([(dt, 5), (dt, 5), (dt, 5), (0.5 * dt, 5), (0.5 * dt, 5), (dt, 3)]):
@@ -76,6 +81,6 @@ def test_batch_graph_replays_match_eager():
             pb, *_ = b.get_state(i)
             assert np.array_equal(pa, pb), (rep, i)
             assert oa[i]["norm"] == ob[i]["norm"]
-        print(f"[graph] batch call {rep} (dt {h}, {n} steps): replay == eager", flush=True)
+        print(f"[graph] batch shape {shape} call {rep} (dt {h}, {n} steps): replay == eager", flush=True)
     a.close()
     b.close()
