@@ -89,16 +89,20 @@ def run_cpu_baseline(name):
             "sample": f"{desc}, FP64 NumPy, {dt:.1f} s"}
 
 
+# Sources the single-grid sweep kernels and their launches are built from (the
+# batch, streaming and adjoint engines live in the .inc files and do not enter them).
+GRID_SOURCES = ("mgso.hip", "mgso_common.h", "mgso_kernels.h", "mgso_sweep.h", "mgso_sweep16.h")
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources (sorted by name): counters measured on other
-    sources no longer describe the kernels."""
+    """sha256 over the sources of the single-grid kernels (sorted by name):
+    counters measured on other sources no longer describe the kernels."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".h", ".hip", ".inc")):
-            h.update(f.encode())
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(GRID_SOURCES):
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -166,7 +170,8 @@ def batch_run(ws, precision, steps, warmup, autotune=True):
     if autotune:
         # the batch's own autotuner picks the launch shape (outside the timed region)
         k, ms = b.autotune(ws[0]["dt"], 10)
-        tuned = {"threads": b.config(k)[0], "tile": b.config(k)[1],
+        tuned = {"shape": int(k), "threads": b.config(k)[0], "tile": b.config(k)[1],
+                 "streaming": bool(k == b.N_CONFIGS - 1),
                  "probe_ms_per_step": {f"{t}x{l}": round(float(x), 4)
                                        for (t, l), x in zip((b.config(i) for i in range(len(ms))), ms)}}
         log(f"autotune: {tuned}")
@@ -197,7 +202,8 @@ def main_batch(args):
         "data": "synthetic",
         "config": {"workload": "morse_batch_256_packets", "packets": len(ws), "points": pts,
                    "potential": "morse_repulsion", "composition": "strang", "order": 2, "split": "TVT",
-                   "dt": ws[0]["dt"], "precision": "c64", "launch": "one persistent kernel per call",
+                   "dt": ws[0]["dt"], "precision": "c64",
+                   "launch": "autotuned shape: one persistent kernel per call, or one launch per sweep",
                    "launch_shape": tuned},
     }
     if not args.no_fp64:
