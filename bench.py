@@ -172,8 +172,8 @@ def batch_run(ws, precision, steps, warmup, autotune=True):
         k, ms = b.autotune(ws[0]["dt"], 10)
         tuned = {"shape": int(k), "threads": b.config(k)[0], "tile": b.config(k)[1],
                  "streaming": bool(k == b.N_CONFIGS - 1),
-                 "probe_ms_per_step": {f"{t}x{l}": round(float(x), 4)
-                                       for (t, l), x in zip((b.config(i) for i in range(len(ms))), ms)}}
+                 "probe_ms_per_step": {f"{i}:{b.config(i)[0]}x{b.config(i)[1]}": round(float(x), 4)
+                                       for i, x in enumerate(ms)}}
         log(f"autotune: {tuned}")
     log(f"batch of {b.B} packets, {b.points} points, {precision}; warmup {warmup}")
     if warmup:
