@@ -361,8 +361,9 @@ __device__ __forceinline__ void tile_axis_fft_pp(typename CT<T>::type* a, typena
   }
 }
 
-// FFT of every line of axis `ax` in the tile (all passes of that axis).
-template <typename T, int NTHR, int TM = MGK_TMAX>
+// FFT of every line of axis `ax` in the tile (all passes of that axis).  WIDE
+// adds the composite radices 9, 10, 12, 15 and 16 (plans made with wide radices).
+template <typename T, int NTHR, int TM = MGK_TMAX, bool WIDE = false>
 __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_t Tn,
                                               const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
                                               const typename CT<T>::type* tw,
@@ -378,6 +379,21 @@ __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_
       case 3: stockham_pass<T, 3, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
       case 4: stockham_pass<T, 4, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
       case 5: stockham_pass<T, 5, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
+      case 9:
+        if constexpr (WIDE) stockham_pass<T, 9, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj);
+        break;
+      case 10:
+        if constexpr (WIDE) stockham_pass<T, 10, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj);
+        break;
+      case 12:
+        if constexpr (WIDE) stockham_pass<T, 12, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj);
+        break;
+      case 15:
+        if constexpr (WIDE) stockham_pass<T, 15, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj);
+        break;
+      case 16:
+        if constexpr (WIDE) stockham_pass<T, 16, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj);
+        break;
       default: stockham_pass<T, 8, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
     }
   }

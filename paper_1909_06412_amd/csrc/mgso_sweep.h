@@ -80,7 +80,7 @@ __device__ __forceinline__ bool tile_elem(const TileDec& sw, const TileOrigin& t
 // pointwise epilogue and store to dst.  acc collects the epilogue's FP64 sums.
 // PP: the transforms ping-pong between lds[0, TM) and lds[TM, 2 TM) (out-of-place
 // Stockham passes); the tile is back in lds[0, TM) after the epilogue.
-template <typename T, int NTHR, int TM = MGK_TMAX, bool PP = false, int DT = 0>
+template <typename T, int NTHR, int TM = MGK_TMAX, bool PP = false, int DT = 0, bool WIDE = false>
 __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const PacketGeom& G, int si, uint32_t tile,
                                              const typename CT<T>::type* src, typename CT<T>::type* dst,
                                              const Tables<T>& tb, int dir, int epi, double h,
@@ -113,10 +113,11 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
         tile_axis_fft_pp<T, NTHR>(lds, lds + TM, &cur, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
                                   tb.A + ax.tab_off, true);
     } else if (!inv) {
-      tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off, nullptr, false);
+      tile_axis_fft<T, NTHR, TM, WIDE>(lds, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off, nullptr,
+                                       false);
     } else {
-      tile_axis_fft<T, NTHR, TM>(lds, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
-                             tb.A + ax.tab_off, true);
+      tile_axis_fft<T, NTHR, TM, WIDE>(lds, Tn, ax, sw.S[ai], sw.dS[ai], true, tw, tb.M + ax.tab_off,
+                                       tb.A + ax.tab_off, true);
     }
   }
   // after an odd number of ping-pong passes the tile sits in the second buffer;
