@@ -150,3 +150,27 @@ def test_launch_shapes_c128():
         print(f"[batch] c128 shape {k} {b.config(k)}: worst packet error vs oracle {worst:.3e}", flush=True)
         assert worst < 1e-12
         b.close()
+
+
+@pytest.mark.parametrize("split,comp,order", [("VTV", "strang", 2), ("TVT", "suzuki", 4), ("VTV", "triple_jump", 4)])
+def test_streaming_shape_schemes(split, comp, order):
+    """The streaming launch shape (one launch per sweep over every packet's tiles,
+    potential-only units as one pointwise launch) follows the oracle for both splits
+    and higher-order compositions, complex128 at the double-precision bar."""
+    mg = _mg()
+    ws = _batch_workloads(split, comp, order, "c128")
+    nsteps = 6
+    b = mg.batch_from_workloads(ws, precision="c128")
+    b.set_config(mg.MovingGridBatch.N_CONFIGS - 1)
+    b.step(ws[0]["dt"], nsteps)
+    worst = 0.0
+    for i, w in enumerate(ws):
+        wp = oracle_packet(w, nsteps)
+        psi, q, p, t = b.get_state(i)
+        ref = wp.physical()
+        worst = max(worst, np.linalg.norm(psi - ref) / np.linalg.norm(ref))
+        assert np.max(np.abs(q - wp.q_ctr)) < 1e-11 and np.max(np.abs(p - wp.p_ctr)) < 1e-11
+        assert abs(t - nsteps * ws[0]["dt"]) < 1e-12
+    print(f"[batch] streaming shape {split} {comp} {order}: worst packet error vs oracle {worst:.3e}", flush=True)
+    assert worst < 1e-12
+    b.close()
