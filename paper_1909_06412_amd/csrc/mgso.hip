@@ -649,15 +649,16 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
 template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, const S16Args<T>& a, int grid) {
   typedef typename CT<T>::type C;
   const size_t lds = k16_lds_bytes<T>(K, INV);
+  const dim3 nt(k16_threads(K));
   if constexpr (EPI == EPI_V) {
     switch (c->pot.kind) {
-      case MG_POT_FREE: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 0>), dim3(grid), dim3(256), lds, c->stream, a); break;
-      case MG_POT_HARMONIC: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 1>), dim3(grid), dim3(256), lds, c->stream, a); break;
-      case MG_POT_HENON_HEILES: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 3>), dim3(grid), dim3(256), lds, c->stream, a); break;
-      default: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 4>), dim3(grid), dim3(256), lds, c->stream, a); break;
+      case MG_POT_FREE: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 0>), dim3(grid), nt, lds, c->stream, a); break;
+      case MG_POT_HARMONIC: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 1>), dim3(grid), nt, lds, c->stream, a); break;
+      case MG_POT_HENON_HEILES: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 3>), dim3(grid), nt, lds, c->stream, a); break;
+      default: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 4>), dim3(grid), nt, lds, c->stream, a); break;
     }
   } else {
-    hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI>), dim3(grid), dim3(256), lds, c->stream, a);
+    hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI>), dim3(grid), nt, lds, c->stream, a);
   }
 }
 
@@ -994,9 +995,18 @@ static void setup_fast16(mg_ctx* c) {
     d.ltiles_i = ilog2u(sw.tiles_i);
     if (d.lr < 0 || d.lI < 0 || d.lLG < 0 || d.ltiles_i < 0) return;
     if (sw.kind == 1 && sw.I % sw.r) return;
-    for (int e = 0; e < d.K; ++e) d.lS[e] = 4 * (d.K - 1 - e) + d.lr;
     d.tiles_i = sw.tiles_i;
     d.ntiles = sw.ntiles;
+    if (sw.kind == 1) {
+      // the 16-point kernels take strided tiles of 8192 points: twice the run of
+      // the generic 4096-point plan (the group tables do not depend on the run)
+      if (sw.I % (2 * sw.r) || sw.tiles_i % 2) return;
+      d.lr += 1;
+      d.tiles_i = sw.tiles_i / 2;
+      d.ltiles_i -= 1;
+      d.ntiles = sw.ntiles / 2;
+    }
+    for (int e = 0; e < d.K; ++e) d.lS[e] = 4 * (d.K - 1 - e) + d.lr;
     d.gtab_off = off;
     sw.gtab_off = off;
     off += (int)sw.LG;

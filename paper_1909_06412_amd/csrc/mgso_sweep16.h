@@ -1,10 +1,12 @@
 // mgso_sweep16.h -- sweep kernel for packets whose axes all have 16 points
 // (the 8-D Henon-Heiles grid 16^8 and any 16^D, D >= 3).
 //
-// A tile holds 4096 points: the K group axes of the sweep (16^K points) times a
-// run of r = 4096 / 16^K consecutive inner indices (r = 1 when the group contains
-// the innermost axis).  256 threads; for every group axis there are exactly 256
-// lines of 16 points, one per thread, transformed by a radix-16 DFT in registers.
+// A contiguous tile (K = 3, the innermost three axes) holds 16^3 = 4096 points and
+// is worked by 256 threads; a strided tile holds the K < 3 group axes of the sweep
+// (16^K points) times a run of r = 8192 / 16^K consecutive inner indices and is
+// worked by 512 threads (the longer runs, 256 bytes and up, keep the memory
+// system busier at large strides).  For every group axis there is exactly one
+// line of 16 points per thread, transformed by a radix-16 DFT in registers.
 // Axes are taken outermost first: the first one is loaded straight from HBM into
 // registers (lanes run along its large stride, so a wave reads whole 128-byte
 // lines); the others go through LDS; the last one is stored straight from
@@ -284,18 +286,25 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
 // when there are transposes, then (strided tiles) the group tables of the sweep:
 // the pre-multiplication (forward A, inverse M) and, inverse, the conj(A) factors
 // of the store.  The final FP64 reduction reuses the start of the buffer.
+// Threads of a k_sweep16 workgroup and points of its tile (16 per thread).
+__host__ __device__ constexpr int k16_threads(int K) { return K < 3 ? 512 : 256; }
+// Padded tile (pad16 gaps) when there are transposes through LDS.
+__host__ __device__ constexpr uint32_t k16_tile_lds(int K) {
+  return K > 1 ? (uint32_t)(16 * k16_threads(K)) + (uint32_t)k16_threads(K) : 0u;
+}
 __host__ __device__ constexpr uint32_t k16_lds_elems(int K, bool INV) {
-  return (K > 1 ? 4352u : 0u) + (K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u);
+  return k16_tile_lds(K) + (K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u);
 }
 template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, bool INV) {
   const size_t b = (size_t)k16_lds_elems(K, INV) * 2 * sizeof(T);
-  const size_t red = (size_t)(256 / 64) * MGK_NACC * sizeof(double);
+  const size_t red = (size_t)(k16_threads(K) / 64) * MGK_NACC * sizeof(double);
   return b > red ? b : red;
 }
 
 template <typename T, int K, bool INV, int EPI, int PK = -1>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__(k16_threads(K)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sweep16(S16Args<T> a) {
+  constexpr int NT = k16_threads(K);
   typedef typename CT<T>::type C;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
@@ -319,10 +328,10 @@ void k_sweep16(S16Args<T> a) {
   if (EPI == EPI_V) stage_line_cst(lc, G, *a.st, *a.pot);
   // Strided tiles keep the sweep's group tables (16^K entries) in LDS for the
   // whole launch; the table index of a thread's points is the same in every tile.
-  C* __restrict__ ltab = lds + (K > 1 ? 4352 : 0);
+  C* __restrict__ ltab = lds + k16_tile_lds(K);
   C* __restrict__ lsto = ltab + (1u << (4 * K));
   if constexpr (KIND == 1) {
-    for (uint32_t i = t; i < (1u << (4 * K)); i += 256) {
+    for (uint32_t i = t; i < (1u << (4 * K)); i += NT) {
       ltab[i] = INV ? MG[i] : AG[i];
       if (INV) lsto[i] = AG[i];
     }
@@ -553,7 +562,7 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
       for (int k = 0; k < MGK_NACC; ++k) acc[k] *= sc;
     }
-    block_reduce<256>(acc, D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
+    block_reduce<NT>(acc, D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
   }
 }
 
