@@ -51,8 +51,8 @@ __global__ __launch_bounds__(NTHR) void k_sweep(SweepArgs<T> a) {
 #pragma unroll
   for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
   for (uint32_t tile = blockIdx.x; tile < sw.ntiles; tile += gridDim.x)
-    process_tile<T, NTHR>(lds, G, a.si, tile, a.src, a.dst, a.tb, a.dir, a.epi, a.h, *a.st, *a.pot, acc, true,
-                          true);
+    process_tile<T, NTHR, MGK_TMAX, false, 0, false, 8>(lds, G, a.si, tile, a.src, a.dst, a.tb, a.dir, a.epi, a.h,
+                                                        *a.st, *a.pot, acc, true, true);
   if (a.epi) block_reduce<NTHR>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
 }
 

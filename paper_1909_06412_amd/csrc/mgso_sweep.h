@@ -80,7 +80,9 @@ __device__ __forceinline__ bool tile_elem(const TileDec& sw, const TileOrigin& t
 // pointwise epilogue and store to dst.  acc collects the epilogue's FP64 sums.
 // PP: the transforms ping-pong between lds[0, TM) and lds[TM, 2 TM) (out-of-place
 // Stockham passes); the tile is back in lds[0, TM) after the epilogue.
-template <typename T, int NTHR, int TM = MGK_TMAX, bool PP = false, int DT = 0, bool WIDE = false>
+// LCH: loads issued per thread before the first is waited for (1: one at a time,
+// for kernels whose registers are already full).
+template <typename T, int NTHR, int TM = MGK_TMAX, bool PP = false, int DT = 0, bool WIDE = false, int LCH = 1>
 __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const PacketGeom& G, int si, uint32_t tile,
                                              const typename CT<T>::type* src, typename CT<T>::type* dst,
                                              const Tables<T>& tb, int dir, int epi, double h,
@@ -92,11 +94,26 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
   const uint32_t Tn = sw.T;
   const TileDec td = tile_dec(sw);
   if (do_load) {
-    for (uint32_t t = threadIdx.x; t < Tn; t += NTHR) {
-      uint64_t gofs;
-      uint32_t g, o, i;
-      const bool ok = tile_elem(td, to, t, &gofs, &g, &o, &i);
-      lds[t] = ok ? gload(src, gofs) : C{(T)0, (T)0};
+    // loads in groups of CH per thread, all issued before the first is waited for
+    // (a loop that stores each value to LDS as it arrives waits once per element)
+    constexpr int CH = LCH;
+    for (uint32_t t0 = threadIdx.x; t0 < Tn; t0 += CH * NTHR) {
+      C v[CH];
+#pragma unroll
+      for (int m = 0; m < CH; ++m) {
+        const uint32_t t = t0 + (uint32_t)(m * NTHR);
+        v[m] = C{(T)0, (T)0};
+        if (t < Tn) {
+          uint64_t gofs;
+          uint32_t g, o, i;
+          if (tile_elem(td, to, t, &gofs, &g, &o, &i)) v[m] = gload(src, gofs);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < CH; ++m) {
+        const uint32_t t = t0 + (uint32_t)(m * NTHR);
+        if (t < Tn) lds[t] = v[m];
+      }
     }
     __syncthreads();
   }
