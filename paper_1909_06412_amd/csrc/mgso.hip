@@ -1015,6 +1015,26 @@ static void setup_fast16(mg_ctx* c) {
   G.fast16 = 1;
 }
 
+// Tile size of a single grid.  Each tile of a sweep is one workgroup, so a small
+// grid (a few tiles of 4096 points) leaves most of the device idle and every
+// launch waits for a few long workgroups: halve the tile (not below 1024 points
+// nor below the longest axis) until a sweep has 128 tiles.  Grids of 16-point
+// axes keep 4096 (the 16-point kernels' tile).
+static uint32_t single_tile_points(int D, const int32_t* N) {
+  uint64_t tot = 1;
+  int32_t maxn = 1;
+  bool all16 = D >= 3;
+  for (int l = 0; l < D; ++l) {
+    tot *= (uint64_t)std::max(N[l], 1);
+    maxn = std::max(maxn, N[l]);
+    if (N[l] != 16) all16 = false;
+  }
+  uint32_t t = MGK_TMAX;
+  if (all16) return t;
+  while (t > 1024 && tot / t < 128 && (int32_t)(t / 2) >= maxn) t /= 2;
+  return t;
+}
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1033,7 +1053,7 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   c->csize = prec == MG_C64 ? 8 : 16;
   std::map<int, int> tw_offs;
   int tw_total = 0;
-  if (!build_geom(D, N, dq, inv_mass, hbar, 0, tw_offs, tw_total, c->geom, c->err)) {
+  if (!build_geom(D, N, dq, inv_mass, hbar, 0, tw_offs, tw_total, c->geom, c->err, single_tile_points(D, N))) {
     g_create_err = c->err;
     delete c;
     return MG_EINVAL;
