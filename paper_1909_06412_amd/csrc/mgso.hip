@@ -1017,10 +1017,11 @@ static void setup_fast16(mg_ctx* c) {
 
 // Tile size of a single grid.  Each tile of a sweep is one workgroup, so a small
 // grid (a few tiles of 4096 points) leaves most of the device idle and every
-// launch waits for a few long workgroups: halve the tile (not below 1024 points
-// nor below the longest axis) until a sweep has 128 tiles.  Grids of 16-point
-// axes keep 4096 (the 16-point kernels' tile).
-static uint32_t single_tile_points(int D, const int32_t* N) {
+// launch waits for a few long workgroups: halve the tile (not below 512 points
+// nor below the longest axis) until a sweep has 128 tiles, as long as the plan
+// keeps its number of sweeps.  Grids of 16-point axes keep 4096 (the 16-point
+// kernels' tile).
+static uint32_t single_tile_points(int D, const int32_t* N, const double* dq, const double* minv, double hbar) {
   uint64_t tot = 1;
   int32_t maxn = 1;
   bool all16 = D >= 3;
@@ -1031,7 +1032,15 @@ static uint32_t single_tile_points(int D, const int32_t* N) {
   }
   uint32_t t = MGK_TMAX;
   if (all16) return t;
-  while (t > 1024 && tot / t < 128 && (int32_t)(t / 2) >= maxn) t /= 2;
+  auto sweeps = [&](uint32_t tm) -> int {
+    std::map<int, int> offs;
+    int total = 0;
+    std::string e;
+    PacketGeom g;
+    return build_geom(D, N, dq, minv, hbar, 0, offs, total, g, e, tm) ? g.nsweeps : -1;
+  };
+  const int ns = sweeps(t);
+  while (t > 512 && tot / t < 128 && (int32_t)(t / 2) >= maxn && sweeps(t / 2) == ns) t /= 2;
   return t;
 }
 
@@ -1053,7 +1062,8 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   c->csize = prec == MG_C64 ? 8 : 16;
   std::map<int, int> tw_offs;
   int tw_total = 0;
-  if (!build_geom(D, N, dq, inv_mass, hbar, 0, tw_offs, tw_total, c->geom, c->err, single_tile_points(D, N))) {
+  if (!build_geom(D, N, dq, inv_mass, hbar, 0, tw_offs, tw_total, c->geom, c->err,
+                  single_tile_points(D, N, dq, inv_mass, hbar))) {
     g_create_err = c->err;
     delete c;
     return MG_EINVAL;
