@@ -82,8 +82,10 @@ typedef enum {
 
 /* Options for mg_set_option. */
 typedef enum {
-  MG_OPT_ENGINE = 1,         /* 0 = automatic, 1 = grid-wide sweeps (one kernel per sweep),
-                                2 = one workgroup per packet (persistent)                 */
+  MG_OPT_ENGINE = 1,         /* sweep kernels of a single grid: 0 = automatic (the radix-16
+                                register kernels when D >= 3 and every axis has 16
+                                points, else the Stockham LDS sweeps), 1 = the Stockham
+                                LDS sweeps for every grid                                 */
   MG_OPT_GRAPH = 2,          /* 1 = capture the launches of mg_step / mg_batch_step once
                                 per (dt, nsteps) as a hipGraph and replay it; any set_*
                                 or option call re-captures on the next step              */

@@ -676,7 +676,8 @@ template <typename T>
 static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk,
                               bool fast = false) {
   typedef typename CT<T>::type C;
-  if (fast && c->geom.fast16 && pot_is_cubic(c->pot.kind) && (epi == 0 || epi == EPI_REDP || epi == EPI_V)) {
+  if (fast && c->opt_engine == 0 && c->geom.fast16 && pot_is_cubic(c->pot.kind) &&
+      (epi == 0 || epi == EPI_REDP || epi == EPI_V)) {
     S16Args<T> a;
     a.geom = c->d_geom;
     a.st = c->d_st;
@@ -1421,7 +1422,7 @@ mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
   if (!c) return MG_EINVAL;
   ++c->version;
   switch (option) {
-    case MG_OPT_ENGINE: if (value < 0 || value > 2) return fail(c, MG_EINVAL, "engine 0..2"); c->opt_engine = (int)value; break;
+    case MG_OPT_ENGINE: if (value < 0 || value > 1) return fail(c, MG_EINVAL, "engine 0..1"); c->opt_engine = (int)value; break;
     case MG_OPT_GRAPH: c->opt_graph = value != 0; break;
     case MG_OPT_PROFILE: c->opt_profile = value != 0; break;
     case MG_OPT_RENORMALIZE: c->opt_renorm = value != 0; break;

@@ -266,3 +266,33 @@ def test_secrest_johnson_model_tenth_order_vtv():
     print(f"[parity] secrest-johnson: E_gpu {ob['Ekin'] + ob['Epot']:.15f} E_oracle {oo['E']:.15f}", flush=True)
     assert abs(ob["Ekin"] + ob["Epot"] - oo["E"]) < 1e-11 * abs(oo["E"])
     assert e < TOL128
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_generic_engine_on_sixteen_point_grid(precision):
+    """MG_OPT_ENGINE = 1 runs a 16^4 grid through the Stockham LDS sweeps instead of
+    the radix-16 register kernels; both follow the oracle."""
+    mg = _mg()
+    w = W.henon_heiles_8d(n=16, D=4, dq=0.625)
+    w["q0"] = [2.0 - 0.1 * l for l in range(4)]
+    nsteps = 3
+    wp, _ = oracle_run(w, nsteps)
+    ref = wp.physical()
+    out = []
+    for engine in (0, 1):
+        m = mg.from_workload(w, precision=precision)
+        m.set_option(mg.MG_OPT_ENGINE, engine)
+        m.step(w["dt"], nsteps)
+        psi, q, p, _ = m.get_state()
+        e = rel_err(psi, ref)
+        print(f"[parity] 16^4 engine {engine} {precision}: state {e:.3e}", flush=True)
+        assert e < (TOL128 if precision == "c128" else TOL64)
+        assert np.max(np.abs(q - wp.q_ctr)) < (1e-12 if precision == "c128" else 1e-6)
+        out.append(psi)
+        m.close()
+    with pytest.raises(mg.MgError):
+        m = mg.from_workload(w, precision=precision)
+        try:
+            m.set_option(mg.MG_OPT_ENGINE, 2)
+        finally:
+            m.close()
