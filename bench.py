@@ -107,14 +107,14 @@ def kernel_source_hash() -> str:
 
 
 def kernel_label(w, precision, cls):
-    """Kernel template name of a profiled sweep class (sweep, dir, epi, group axes)."""
-    _, d, epi, k = cls
+    """Kernel template name of a profiled sweep class (sweep, dir, epi, group axes, mode)."""
+    _, d, epi, k, mode = cls
     t = "float" if precision == "c64" else "double"
     fast16 = w["D"] >= 3 and all(n == 16 for n in w["N"]) and w["potential"][0] != "morse_repulsion"
     if not fast16:
         return f"k_sweep<{t}>"
     pk = POT_KIND[w["potential"][0]] if epi == 4 else -1
-    return f"k_sweep16<{t}, {k}, {'true' if d else 'false'}, {epi}, {pk}>"
+    return f"k_sweep16<{t}, {k}, {'true' if d else 'false'}, {epi}, {pk}, {mode}>"
 
 
 def measured_traffic(w, precision, label):

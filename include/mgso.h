@@ -187,16 +187,21 @@ mg_status mg_set_option(mg_ctx* ctx, int option, int64_t value);
 
 /* Kernel timing collected under MG_OPT_PROFILE since the last reset:
  * for the sweep kernel class with the largest total time, its launch count, total
- * milliseconds and algorithmic bytes per launch (2 x N x bytes per complex).
+ * milliseconds and algorithmic bytes per launch (2 x N x bytes per complex; 1 x for
+ * a moments-only sweep, which stores nothing).
  * reset != 0 clears the counters after reading. */
 mg_status mg_profile_read(mg_ctx* ctx, int64_t* launches, double* total_ms,
                           double* bytes_per_launch, int reset);
 /* The kernel class that mg_profile_read reports (read it before a reset): sweep
  * index (0 = the sweep over the innermost axes), dir (0 forward, 1 inverse), the
  * epilogue flags of that sweep (1: momentum moments, 4: potential substep) and the
- * number of axes the sweep transforms together.  All outputs -1 when nothing has
+ * number of axes the sweep transforms together, and its mode: 0 an ordinary sweep,
+ * 1 the moments-only forward sweep and 2 the round-trip inverse sweep (forward DFT,
+ * kinetic factor, inverse DFT) that 16-point grids use for the outermost sweep of a
+ * kinetic substep when it transforms one axis.  All outputs -1 when nothing has
  * been profiled.  Any output pointer may be NULL. */
-mg_status mg_profile_class(const mg_ctx* ctx, int* sweep, int* dir, int* epi, int* group_axes);
+mg_status mg_profile_class(const mg_ctx* ctx, int* sweep, int* dir, int* epi, int* group_axes,
+                           int* mode);
 
 /* Autocorrelation <psi_0|psi_t> (Sec. III.C): psi_0 is the Gaussian of
  * mg_set_gaussian with these parameters (q0, p0, sigma each [D]), evaluated

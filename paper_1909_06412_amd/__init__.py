@@ -61,6 +61,7 @@ class MovingGrid:
     def __init__(self, N, dq, inv_mass, hbar=1.0, precision="c128", use_torch=True):
         self.D = len(N)
         self.N = [int(n) for n in N]
+        self.dq = [float(x) for x in np.asarray(dq, dtype=np.float64).reshape(-1)]
         self.precision = precision
         lib = L.lib()
         stream, torch = _torch_stream_and_alloc() if use_torch else (None, None)
@@ -112,6 +113,25 @@ class MovingGrid:
         L.check(L.lib().mg_get_state(self.h, L.dptr(psi.view(np.float64).reshape(-1)), L.dptr(q),
                                      L.dptr(p), L.dptr(t)), self.h)
         return psi, q, p, float(t[0])
+
+    def centres(self):
+        """(q_ctr, p_ctr, t) without copying the state."""
+        q = np.empty(self.D)
+        p = np.empty(self.D)
+        t = np.empty(1)
+        L.check(L.lib().mg_get_state(self.h, None, L.dptr(q), L.dptr(p), L.dptr(t)), self.h)
+        return q, p, float(t[0])
+
+    def state_view(self):
+        """The bound device state as a flat torch complex tensor of N_total elements
+        (row-major, axis 0 outermost), holding psi(q) * sqrt(prod dq); None without
+        torch buffers.  A view, not a copy: read it between steps only."""
+        if not self._bufs:
+            return None
+        import torch
+        n = int(np.prod(self.N))
+        dt = torch.complex64 if self.precision == "c64" else torch.complex128
+        return self._bufs[0].view(dt)[:n]
 
     # --- model -----------------------------------------------------------
     def set_potential(self, kind, params):
@@ -165,8 +185,8 @@ class MovingGrid:
         return complex(out[0], out[1])
 
     def profile_class(self):
-        """(sweep, dir, epi, group_axes) of the kernel class profile_read reports."""
-        v = [L.C.c_int() for _ in range(4)]
+        """(sweep, dir, epi, group_axes, mode) of the kernel class profile_read reports."""
+        v = [L.C.c_int() for _ in range(5)]
         L.check(L.lib().mg_profile_class(self.h, *[L.C.byref(x) for x in v]), self.h)
         return tuple(x.value for x in v)
 

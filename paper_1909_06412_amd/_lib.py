@@ -50,7 +50,7 @@ _SIGS = {
     "mg_regrid": (C.c_int, [_vp, _dp]),
     "mg_set_option": (C.c_int, [_vp, C.c_int, C.c_int64]),
     "mg_profile_read": (C.c_int, [_vp, _i64p, _dp, _dp, C.c_int]),
-    "mg_profile_class": (C.c_int, [_vp, _ip, _ip, _ip, _ip]),
+    "mg_profile_class": (C.c_int, [_vp, _ip, _ip, _ip, _ip, _ip]),
     "mg_autocorrelation": (C.c_int, [_vp, _dp, _dp, _dp, _dp]),
     "mg_spectrum": (C.c_int, [_dp, _dp, C.c_int, _dp, C.c_int, C.c_double, C.c_double, _dp]),
     "mg_adjoint": (C.c_int, [_vp, C.c_double, C.c_int64, C.c_int, _dp, _ip, C.c_int, _dp, _dp]),

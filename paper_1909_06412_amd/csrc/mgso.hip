@@ -646,10 +646,23 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
   return MG_OK;
 }
 
-template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, const S16Args<T>& a, int grid) {
+template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, const S16Args<T>& a, int grid,
+                                                                     int mode) {
   typedef typename CT<T>::type C;
   const size_t lds = k16_lds_bytes<T>(K, INV);
   const dim3 nt(k16_threads(K));
+  if constexpr (K == 1 && !INV && EPI == EPI_REDP) {
+    if (mode == SW_MOMENTS) {
+      hipLaunchKernelGGL((k_sweep16<T, 1, false, EPI_REDP, -1, SW_MOMENTS>), dim3(grid), nt, lds, c->stream, a);
+      return;
+    }
+  }
+  if constexpr (K == 1 && INV && EPI == 0) {
+    if (mode == SW_ROUNDTRIP) {
+      hipLaunchKernelGGL((k_sweep16<T, 1, true, 0, -1, SW_ROUNDTRIP>), dim3(grid), nt, lds, c->stream, a);
+      return;
+    }
+  }
   if constexpr (EPI == EPI_V) {
     switch (c->pot.kind) {
       case MG_POT_FREE: hipLaunchKernelGGL((k_sweep16<T, K, INV, EPI, 0>), dim3(grid), nt, lds, c->stream, a); break;
@@ -662,22 +675,38 @@ template <typename T, int K, bool INV, int EPI> static void launch16(mg_ctx* c, 
   }
 }
 
-template <typename T, bool INV, int EPI> static void launch16_k(mg_ctx* c, const S16Args<T>& a, int grid) {
+template <typename T, bool INV, int EPI>
+static void launch16_k(mg_ctx* c, const S16Args<T>& a, int grid, int mode) {
   switch (a.d.K) {
-    case 1: launch16<T, 1, INV, EPI>(c, a, grid); break;
-    case 2: launch16<T, 2, INV, EPI>(c, a, grid); break;
-    default: launch16<T, 3, INV, EPI>(c, a, grid); break;
+    case 1: launch16<T, 1, INV, EPI>(c, a, grid, mode); break;
+    case 2: launch16<T, 2, INV, EPI>(c, a, grid, mode); break;
+    default: launch16<T, 3, INV, EPI>(c, a, grid, mode); break;
   }
 }
 
+// The 16-point kernels run a propagation step's sweeps (plain, REDP and V epilogues).
+static bool fast16_step(const mg_ctx* c) {
+  return c->opt_engine == 0 && c->geom.fast16 && pot_is_cubic(c->pot.kind);
+}
+// A kinetic substep of such a step turns round on its outermost sweep (moments-only
+// forward, round-trip inverse) when that sweep is a one-axis strided sweep.
+static bool fast16_turn(const mg_ctx* c) {
+  const int ns = c->geom.nsweeps;
+  return fast16_step(c) && ns >= 2 && c->s16[ns - 1].K == 1 && c->s16[ns - 1].kind == 1;
+}
+
 // Launch sweep si; returns the number of blocks (for the finalize).  fast = use
-// the 16-point kernel when the packet qualifies (only plain, REDP and V epilogues).
+// the 16-point kernel when the packet qualifies (only plain, REDP and V epilogues);
+// mode SW_MOMENTS / SW_ROUNDTRIP only where fast16_turn holds.
 template <typename T>
 static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk,
-                              bool fast = false) {
+                              bool fast = false, int mode = SW_FULL) {
   typedef typename CT<T>::type C;
-  if (fast && c->opt_engine == 0 && c->geom.fast16 && pot_is_cubic(c->pot.kind) &&
-      (epi == 0 || epi == EPI_REDP || epi == EPI_V)) {
+  if (mode != SW_FULL &&
+      !(fast && fast16_turn(c) && si == c->geom.nsweeps - 1 &&
+        (mode == SW_MOMENTS ? dir == DIR_FWD && epi == EPI_REDP : dir == DIR_INV && epi == 0)))
+    return fail(c, MG_EINVAL, "internal: turning sweep requested where the plan has none");
+  if (fast && fast16_step(c) && (epi == 0 || epi == EPI_REDP || epi == EPI_V)) {
     S16Args<T> a;
     a.geom = c->d_geom;
     a.st = c->d_st;
@@ -699,16 +728,16 @@ static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, con
     }
     const bool inv = dir == DIR_INV;
     if (!inv) {
-      if (epi == EPI_REDP) launch16_k<T, false, EPI_REDP>(c, a, grid);
-      else launch16_k<T, false, 0>(c, a, grid);
+      if (epi == EPI_REDP) launch16_k<T, false, EPI_REDP>(c, a, grid, mode);
+      else launch16_k<T, false, 0>(c, a, grid, mode);
     } else {
-      if (epi == EPI_V) launch16_k<T, true, EPI_V>(c, a, grid);
-      else launch16_k<T, true, 0>(c, a, grid);
+      if (epi == EPI_V) launch16_k<T, true, EPI_V>(c, a, grid, mode);
+      else launch16_k<T, true, 0>(c, a, grid, mode);
     }
     HIPCHK(c, hipGetLastError());
     if (c->opt_profile) {
       HIPCHK(c, hipEventRecord(pe.e1, c->stream));
-      pe.cls = si * 64 + dir * 32 + epi;
+      pe.cls = mode * 4096 + si * 64 + dir * 32 + epi;
       c->prof_pending.push_back(pe);
     }
     return MG_OK;
@@ -763,14 +792,17 @@ template <typename T> static mg_status launch_pointwise(mg_ctx* c, int epi, doub
 
 // Forward transform of src into dst (dst may equal src); the last sweep reduces
 // the momentum moments with epilogue `epi_last`.
+// turn: the last sweep only reduces (dst keeps that axis group untransformed; the
+// next inverse_transform must turn too).
 template <typename T>
 static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last,
-                                   bool fast = false) {
+                                   bool fast = false, bool turn = false) {
   const int ns = c->geom.nsweeps;
   for (int s = 0; s < ns; ++s) {
     int nb;
-    mg_status r =
-        launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb, fast);
+    const int mode = turn && s == ns - 1 ? SW_MOMENTS : SW_FULL;
+    mg_status r = launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb,
+                                  fast, mode);
     if (r) return r;
     if (s == ns - 1) *nblk_last = nb;
   }
@@ -779,11 +811,13 @@ static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int ep
 
 template <typename T>
 static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last,
-                                   bool fast = false) {
+                                   bool fast = false, bool turn = false) {
   const int ns = c->geom.nsweeps;
   for (int s = ns - 1; s >= 0; --s) {
     int nb;
-    mg_status r = launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb, fast);
+    const int mode = turn && s == ns - 1 ? SW_ROUNDTRIP : SW_FULL;
+    mg_status r =
+        launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb, fast, mode);
     if (r) return r;
     if (s == 0) *nblk_last = nb;
   }
@@ -794,9 +828,10 @@ template <typename T> static mg_status run_unit(mg_ctx* c, const Unit& u) {
   mg_status r;
   int nb = 0;
   if (u.hasT) {
-    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb, true))) return r;
+    const bool turn = fast16_turn(c);
+    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb, true, turn))) return r;
     if ((r = launch_finalize<T>(c, FIN_T, u.hT, nb, nullptr))) return r;
-    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb, true))) return r;
+    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb, true, turn))) return r;
     if (u.hasV && (r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
   } else if (u.hasV) {
     if ((r = launch_pointwise<T>(c, EPI_V, u.hV, &nb))) return r;
@@ -1442,7 +1477,7 @@ mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
   return MG_OK;
 }
 
-mg_status mg_profile_class(const mg_ctx* c, int* sweep, int* dir, int* epi, int* group_axes) {
+mg_status mg_profile_class(const mg_ctx* c, int* sweep, int* dir, int* epi, int* group_axes, int* mode) {
   if (!c) return MG_EINVAL;
   int best = -1;
   double best_ms = -1;
@@ -1451,11 +1486,12 @@ mg_status mg_profile_class(const mg_ctx* c, int* sweep, int* dir, int* epi, int*
       best_ms = kv.second.second;
       best = kv.first;
     }
-  const int si = best < 0 ? -1 : best / 64;
+  const int si = best < 0 ? -1 : (best & 4095) / 64;
   if (sweep) *sweep = si;
   if (dir) *dir = best < 0 ? -1 : (best / 32) & 1;
   if (epi) *epi = best < 0 ? -1 : best & 31;
   if (group_axes) *group_axes = si < 0 ? -1 : c->geom.sw[si].b - c->geom.sw[si].a;
+  if (mode) *mode = best < 0 ? -1 : best / 4096;
   return MG_OK;
 }
 
@@ -1470,7 +1506,8 @@ mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double
     }
   if (launches) *launches = best < 0 ? 0 : c->prof[best].first;
   if (total_ms) *total_ms = best < 0 ? 0.0 : best_ms;
-  if (bytes) *bytes = 2.0 * (double)c->geom.N_total * (double)c->csize;
+  // a moments-only sweep reads the state once; every other sweep reads and writes it
+  if (bytes) *bytes = (best / 4096 == SW_MOMENTS ? 1.0 : 2.0) * (double)c->geom.N_total * (double)c->csize;
   if (reset) c->prof.clear();
   return MG_OK;
 }

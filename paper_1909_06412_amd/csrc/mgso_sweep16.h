@@ -301,9 +301,21 @@ template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, 
   return b > red ? b : red;
 }
 
-template <typename T, int K, bool INV, int EPI, int PK = -1>
+enum : int { SW_FULL = 0, SW_MOMENTS = 1, SW_ROUNDTRIP = 2 };
+
+// MODE (strided one-axis sweeps only) splits a kinetic substep differently at its
+// turning point, where the last forward sweep meets the first inverse sweep on the
+// same axis group: SW_MOMENTS is that forward sweep reduced to its momentum moments
+// (nothing is stored, the axis stays untransformed in memory), SW_ROUNDTRIP the inverse
+// sweep that then does the forward DFT, the M factor and the inverse DFT of the axis
+// in registers.  Same arithmetic as the two full sweeps, one HBM write and one read
+// fewer.
+template <typename T, int K, bool INV, int EPI, int PK = -1, int MODE = 0>
 __global__ __launch_bounds__(k16_threads(K)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sweep16(S16Args<T> a) {
+  static_assert(MODE == SW_FULL || (K == 1 && (MODE == SW_MOMENTS) == (!INV && EPI == EPI_REDP) &&
+                                    (MODE == SW_ROUNDTRIP) == (INV && EPI == 0)),
+                "moments-only and round-trip sweeps are one-axis strided sweeps");
   constexpr int NT = k16_threads(K);
   typedef typename CT<T>::type C;
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -381,6 +393,7 @@ void k_sweep16(S16Args<T> a) {
     auto tab_stride = [&](uint32_t S_) -> uint32_t { return KIND == 0 ? S_ : (S_ >> d.lr); };
 
     C x[16];
+    C pv[KIND == 1 ? 16 : 1];  // strided inverse: the conj(A) factors of the store
     // ---- first axis: the outermost group axis (largest tile stride), coalesced
     int e = 0;
     uint32_t S = 1u << d.lS[0];
@@ -395,6 +408,16 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = xn[k];
       if (PIPE && KIND == 1 && tile + gridDim.x < d.ntiles) load_first(tile + gridDim.x);
+      if constexpr (MODE == SW_ROUNDTRIP) {
+        // forward half of the round trip: A factor, DFT (the A table also gives the
+        // conj(A) of the store below)
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          pv[k] = lsto[k * ts + glane];
+          x[k] = cmul(x[k], pv[k]);
+        }
+        dft16<T, false>(x);
+      }
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], pre[k * ts + glane]);
       dft16<T, INV>(x);
@@ -417,8 +440,7 @@ void k_sweep16(S16Args<T> a) {
     // overlaps the last DFT and the epilogue
     // (a contiguous tile fetches them after the epilogue instead, to keep the
     // epilogue's registers free; they then overlap the LDS transpose)
-    C pv[KIND == 1 ? 16 : 1];
-    if (INV && KIND == 1) {
+    if (INV && KIND == 1 && MODE != SW_ROUNDTRIP) {
       const uint32_t ts = tab_stride(S);
       const uint32_t glane = g_of(tau0);
 #pragma unroll
@@ -430,6 +452,7 @@ void k_sweep16(S16Args<T> a) {
       // 128-byte segments straight from registers
       const int L = d.a + e;
       if (EPI) line_epilogue<T, EPI, PK>(x, L, flat_of(tau0), D, lc, hh, acc);
+      if (MODE == SW_MOMENTS) continue;
       const uint64_t ms = mem_stride(S);
       const uint32_t lane = (uint32_t)(flat_of(tau0) - flat0);
       C* __restrict__ tdst = dst + flat0;
