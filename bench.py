@@ -91,7 +91,7 @@ def run_cpu_baseline(name):
 
 # Sources the single-grid sweep kernels and their launches are built from (the
 # batch, streaming and adjoint engines live in the .inc files and do not enter them).
-GRID_SOURCES = ("mgso.hip", "mgso_common.h", "mgso_kernels.h", "mgso_sweep.h", "mgso_sweep16.h")
+GRID_SOURCES = ("mgso.hip", "mgso_common.h", "mgso_kernels.h", "mgso_split.h", "mgso_sweep.h", "mgso_sweep16.h")
 
 
 def kernel_source_hash() -> str:
@@ -108,8 +108,11 @@ def kernel_source_hash() -> str:
 
 def kernel_label(w, precision, cls):
     """Kernel template name of a profiled sweep class (sweep, dir, epi, group axes, mode)."""
-    _, d, epi, k, mode = cls
+    si, d, epi, k, mode = cls
     t = "float" if precision == "c64" else "double"
+    if mode >= 3:
+        # passes of the three-pass 16^8 plan: B forward 0, B inverse 1, C moments 2, C round trip 3
+        return f"k_split<{2 if mode == 4 else (d if si == 1 else 3)}>"
     fast16 = w["D"] >= 3 and all(n == 16 for n in w["N"]) and w["potential"][0] != "morse_repulsion"
     if not fast16:
         return f"k_sweep<{t}>"

@@ -84,8 +84,10 @@ typedef enum {
 typedef enum {
   MG_OPT_ENGINE = 1,         /* sweep kernels of a single grid: 0 = automatic (the radix-16
                                 register kernels when D >= 3 and every axis has 16
-                                points, else the Stockham LDS sweeps), 1 = the Stockham
-                                LDS sweeps for every grid                                 */
+                                points, with the three-pass plan for 16^8 complex64
+                                grids; else the Stockham LDS sweeps), 1 = the Stockham
+                                LDS sweeps for every grid, 2 = the radix-16 kernels
+                                without the three-pass plan                               */
   MG_OPT_GRAPH = 2,          /* 1 = capture the launches of mg_step / mg_batch_step once
                                 per (dt, nsteps) as a hipGraph and replay it; any set_*
                                 or option call re-captures on the next step              */
@@ -198,8 +200,10 @@ mg_status mg_profile_read(mg_ctx* ctx, int64_t* launches, double* total_ms,
  * number of axes the sweep transforms together, and its mode: 0 an ordinary sweep,
  * 1 the moments-only forward sweep and 2 the round-trip inverse sweep (forward DFT,
  * kinetic factor, inverse DFT) that 16-point grids use for the outermost sweep of a
- * kinetic substep when it transforms one axis.  All outputs -1 when nothing has
- * been profiled.  Any output pointer may be NULL. */
+ * kinetic substep when it transforms one axis, 3 a pass of the three-pass 16^8
+ * plan (sweep 1: the pass over axes 3, 0 and the high digit of axis 2; sweep 2: axes
+ * 4, 1 and the low digit; group_axes 3), 4 its moments-only forward pass.  All
+ * outputs -1 when nothing has been profiled.  Any output pointer may be NULL. */
 mg_status mg_profile_class(const mg_ctx* ctx, int* sweep, int* dir, int* epi, int* group_axes,
                            int* mode);
 

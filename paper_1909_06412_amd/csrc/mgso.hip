@@ -18,6 +18,7 @@
 #include "mgso.h"
 #include "mgso_sweep.h"
 #include "mgso_sweep16.h"
+#include "mgso_split.h"
 
 using namespace mgk;
 
@@ -197,6 +198,52 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
           C v = C{(decltype(C().x))(mag * c), (decltype(C().x))(mag * s)};
           if (doA) a.AG[sw.gtab_off + g] = v;
           else a.MG[sw.gtab_off + g] = v;
+        }
+      }
+      if (G.split) {
+        // tables of the three-pass 16^8 plan (mgso_split.h): per-axis angles summed
+        // in FP64, as above; A_l(j) carries (-1)^j and 1/4, M_l(k) the momentum
+        // p = p_ctr + (k - 8) dp of Eq. (55)
+        auto angA = [&](int l, int j) {
+          return M_PI * (double)(j & 1) - st.p_c[l] * (double)j * G.ax[l].dq / hbar;
+        };
+        auto angM = [&](int l, int k) {
+          const double p = st.p_c[l] + (double)(k - 8) * G.ax[l].dp;
+          return -(h * 0.5 * G.ax[l].minv * p * p - st.delta[l] * p) / hbar;
+        };
+        const int ys = SPL_SPLIT_AXIS;
+        for (int e = threadIdx.x; e < SPL_TAB; e += NTHR) {
+          double ang, mag = 1.0;
+          if (e < 2048) {
+            const int pass = e >> 10, g = e & 1023;
+            const int X = g & 15, Y = (g >> 4) & 3, Z = g >> 6;
+            const int ax = SPL_AX[pass][0], az = SPL_AX[pass][1];
+            if (doA) {
+              ang = angA(ax, X) + angA(az, Z);
+              mag = 1.0 / 16.0;
+              if (pass == 0) {
+                // high digit n1 = Y of the split axis: its index 4 n1 is even
+                ang -= st.p_c[ys] * (double)(4 * Y) * G.ax[ys].dq / hbar;
+                mag = 1.0 / 64.0;
+              }
+            } else {
+              ang = angM(ax, X) + angM(az, Z);
+            }
+          } else {
+            const int k = e - 2048;
+            if (doA) {
+              // c(n0) W16^(n0 k0) at 4 n0 + k0
+              const int n0 = k >> 2, k0 = k & 3;
+              ang = angA(ys, n0) - 2.0 * M_PI * (double)(n0 * k0) / 16.0;
+            } else {
+              ang = angM(ys, k);
+            }
+          }
+          double sn, cs;
+          sincos(ang, &sn, &cs);
+          const C v = C{(decltype(C().x))(mag * cs), (decltype(C().x))(mag * sn)};
+          if (doA) a.AG[G.gtab_len + e] = v;
+          else a.MG[G.gtab_len + e] = v;
         }
       }
     }
@@ -566,6 +613,8 @@ struct mg_ctx {
   void* d_AG = nullptr;
   void* d_MG = nullptr;
   S16Desc s16[MGK_MAXD];
+  SplitDesc spl[2];  // passes B and C of the three-pass 16^8 plan (geom.split)
+  int n_cu = 0;      // compute units of the device (grid of the split passes)
   double* d_part = nullptr;
   void* psi = nullptr;
   bool psi_owned = false;
@@ -686,7 +735,7 @@ static void launch16_k(mg_ctx* c, const S16Args<T>& a, int grid, int mode) {
 
 // The 16-point kernels run a propagation step's sweeps (plain, REDP and V epilogues).
 static bool fast16_step(const mg_ctx* c) {
-  return c->opt_engine == 0 && c->geom.fast16 && pot_is_cubic(c->pot.kind);
+  return c->opt_engine != 1 && c->geom.fast16 && pot_is_cubic(c->pot.kind);
 }
 // A kinetic substep of such a step turns round on its outermost sweep (moments-only
 // forward, round-trip inverse) when that sweep is a one-axis strided sweep.
@@ -792,12 +841,64 @@ template <typename T> static mg_status launch_pointwise(mg_ctx* c, int epi, doub
 
 // Forward transform of src into dst (dst may equal src); the last sweep reduces
 // the momentum moments with epilogue `epi_last`.
+// The three-pass plan runs a 16^8 complex64 step's kinetic substeps (engine 0).
+static bool split_step(const mg_ctx* c) { return c->opt_engine == 0 && c->geom.split && fast16_turn(c); }
+
+template <int KIND> static void launch_split_k(mg_ctx* c, const SplArgs& a, int grid) {
+  hipLaunchKernelGGL(k_split<KIND>, dim3(grid), dim3(SPL_NT), SPL_LDS_BYTES, c->stream, a);
+}
+
+// One pass of the three-pass plan on buf (in place); kind SPL_*.  One workgroup
+// per compute unit (the tile takes most of the LDS), each looping over its tiles.
+static mg_status launch_split(mg_ctx* c, int kind, void* buf, int* nblk) {
+  SplArgs a;
+  a.geom = c->d_geom;
+  a.src = (const float2*)buf;
+  a.dst = (float2*)buf;
+  a.AG = (const float2*)c->d_AG;
+  a.MG = (const float2*)c->d_MG;
+  a.partials = c->d_part;
+  a.d = c->spl[kind >= SPL_C_MOM ? 1 : 0];
+  const int grid = std::min<int>(c->n_cu > 0 ? c->n_cu : 256, MAX_BLOCKS);
+  *nblk = grid;
+  ProfEntry pe{};
+  if (c->opt_profile) {
+    HIPCHK(c, hipEventCreate(&pe.e0));
+    HIPCHK(c, hipEventCreate(&pe.e1));
+    HIPCHK(c, hipEventRecord(pe.e0, c->stream));
+  }
+  switch (kind) {
+    case SPL_B_FWD: launch_split_k<SPL_B_FWD>(c, a, grid); break;
+    case SPL_B_INV: launch_split_k<SPL_B_INV>(c, a, grid); break;
+    case SPL_C_MOM: launch_split_k<SPL_C_MOM>(c, a, grid); break;
+    default: launch_split_k<SPL_C_RT>(c, a, grid); break;
+  }
+  HIPCHK(c, hipGetLastError());
+  if (c->opt_profile) {
+    HIPCHK(c, hipEventRecord(pe.e1, c->stream));
+    const int mode = kind == SPL_C_MOM ? SW_SPLIT_MOM : SW_SPLIT;
+    const int si = kind >= SPL_C_MOM ? 2 : 1;
+    const int dir = (kind == SPL_B_INV || kind == SPL_C_RT) ? DIR_INV : DIR_FWD;
+    pe.cls = mode * 4096 + si * 64 + dir * 32 + (kind == SPL_C_MOM ? EPI_REDP : 0);
+    c->prof_pending.push_back(pe);
+  }
+  return MG_OK;
+}
+
 // turn: the last sweep only reduces (dst keeps that axis group untransformed; the
 // next inverse_transform must turn too).
 template <typename T>
 static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last,
                                    bool fast = false, bool turn = false) {
   const int ns = c->geom.nsweeps;
+  if (fast && turn && split_step(c)) {
+    if (epi_last != EPI_REDP) return fail(c, MG_EINVAL, "internal: the three-pass plan reduces momentum moments");
+    int nb;
+    mg_status r = launch_sweep<T>(c, 0, DIR_FWD, 0, 0.0, src, dst, &nb, fast);
+    if (!r) r = launch_split(c, SPL_B_FWD, dst, &nb);
+    if (!r) r = launch_split(c, SPL_C_MOM, dst, nblk_last);
+    return r;
+  }
   for (int s = 0; s < ns; ++s) {
     int nb;
     const int mode = turn && s == ns - 1 ? SW_MOMENTS : SW_FULL;
@@ -813,6 +914,13 @@ template <typename T>
 static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last,
                                    bool fast = false, bool turn = false) {
   const int ns = c->geom.nsweeps;
+  if (fast && turn && split_step(c)) {
+    int nb;
+    mg_status r = launch_split(c, SPL_C_RT, buf, &nb);
+    if (!r) r = launch_split(c, SPL_B_INV, buf, &nb);
+    if (!r) r = launch_sweep<T>(c, 0, DIR_INV, epi_first_sweep, hV, buf, buf, nblk_last, fast);
+    return r;
+  }
   for (int s = ns - 1; s >= 0; --s) {
     int nb;
     const int mode = turn && s == ns - 1 ? SW_ROUNDTRIP : SW_FULL;
@@ -1001,6 +1109,18 @@ template <typename T> static hipError_t set_lds_attr16() {
   return e;
 }
 
+static hipError_t set_lds_attr_split() {
+  const int b = (int)SPL_LDS_BYTES;
+  hipError_t e = hipFuncSetAttribute((const void*)k_split<SPL_B_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_split<SPL_B_INV>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_split<SPL_C_MOM>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_split<SPL_C_RT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+  return e;
+}
+
 static int ilog2u(uint64_t v) {
   int l = 0;
   while ((1ull << l) < v) ++l;
@@ -1049,6 +1169,50 @@ static void setup_fast16(mg_ctx* c) {
   }
   G.gtab_len = off;
   G.fast16 = 1;
+}
+
+// The three-pass plan of 16^8 complex64 grids (mgso_split.h): the radix-16 plan
+// must be sweep 0 over axes 5-7 (contiguous tile) and three strided sweeps.
+static void setup_split(mg_ctx* c) {
+  PacketGeom& G = c->geom;
+  G.split = 0;
+  if (!G.fast16 || c->prec != MG_C64 || G.D != 8 || G.nsweeps != 4) return;
+  if (c->s16[0].K != 3 || c->s16[0].a != 5 || c->s16[0].kind != 0) return;
+  const int p2 = 4 * (7 - SPL_SPLIT_AXIS);
+  for (int p = 0; p < 2; ++p) {
+    SplitDesc& d = c->spl[p];
+    memset(&d, 0, sizeof(d));
+    d.axX = SPL_AX[p][0];
+    d.axZ = SPL_AX[p][1];
+    d.axY = SPL_SPLIT_AXIS;
+    d.pX = 4 * (7 - d.axX);
+    d.pZ = 4 * (7 - d.axZ);
+    d.pY = p == 0 ? p2 + 2 : p2;
+    d.pYc = p == 0 ? p2 : p2 + 2;
+    const uint32_t in = 0xFu | (0xFu << d.pX) | (0x3u << d.pY) | (0xFu << d.pZ);
+    // the tile index fills the other 18 bits: maximal runs of them, low first
+    int nf = 0, nb = 0;
+    for (int b = 0; b < 32;) {
+      if ((in >> b) & 1u) {
+        ++b;
+        continue;
+      }
+      int w = 0;
+      while (b + w < 32 && !((in >> (b + w)) & 1u)) ++w;
+      if (nf == 4) return;
+      d.flo[nf] = b;
+      d.fw[nf] = w;
+      ++nf;
+      nb += w;
+      b += w;
+    }
+    if (nb != 18 || __builtin_popcount(in) != 14) return;
+    d.nf = nf;
+    d.ntiles = 1u << 18;
+    d.tab = G.gtab_len + 1024 * p;
+    d.small = G.gtab_len + 2048;
+  }
+  G.split = 1;
 }
 
 // Tile size of a single grid.  Each tile of a sweep is one workgroup, so a small
@@ -1106,6 +1270,7 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   }
   c->geom.off = 0;
   setup_fast16(c);
+  setup_split(c);
   c->pot.kind = MG_POT_FREE;
   c->pot.D = D;
   hipError_t e = hipSuccess;
@@ -1117,11 +1282,18 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   if (e == hipSuccess) e = hipMalloc(&c->d_A, (size_t)c->geom.tab_len * c->csize);
   if (e == hipSuccess) e = hipMalloc(&c->d_M, (size_t)c->geom.tab_len * c->csize);
   if (e == hipSuccess) e = hipMalloc(&c->d_part, (size_t)MAX_BLOCKS * MGK_NACC * sizeof(double));
-  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, (size_t)c->geom.gtab_len * c->csize);
-  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, (size_t)c->geom.gtab_len * c->csize);
+  const size_t gtab = (size_t)c->geom.gtab_len + (c->geom.split ? SPL_TAB : 0);
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, gtab * c->csize);
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, gtab * c->csize);
   if (e == hipSuccess && c->geom.fast16) {
     where = "hipFuncSetAttribute";
     e = prec == MG_C128 ? set_lds_attr16<double>() : set_lds_attr16<float>();
+  }
+  if (e == hipSuccess && c->geom.split) e = set_lds_attr_split();
+  if (e == hipSuccess && c->geom.split) {
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   }
   if (e == hipSuccess) where = "hipMemcpy";
   if (e == hipSuccess) e = hipMemcpy(c->d_geom, &c->geom, sizeof(PacketGeom), hipMemcpyHostToDevice);
@@ -1457,7 +1629,7 @@ mg_status mg_set_option(mg_ctx* c, int option, int64_t value) {
   if (!c) return MG_EINVAL;
   ++c->version;
   switch (option) {
-    case MG_OPT_ENGINE: if (value < 0 || value > 1) return fail(c, MG_EINVAL, "engine 0..1"); c->opt_engine = (int)value; break;
+    case MG_OPT_ENGINE: if (value < 0 || value > 2) return fail(c, MG_EINVAL, "engine 0..2"); c->opt_engine = (int)value; break;
     case MG_OPT_GRAPH: c->opt_graph = value != 0; break;
     case MG_OPT_PROFILE: c->opt_profile = value != 0; break;
     case MG_OPT_RENORMALIZE: c->opt_renorm = value != 0; break;
@@ -1490,7 +1662,7 @@ mg_status mg_profile_class(const mg_ctx* c, int* sweep, int* dir, int* epi, int*
   if (sweep) *sweep = si;
   if (dir) *dir = best < 0 ? -1 : (best / 32) & 1;
   if (epi) *epi = best < 0 ? -1 : best & 31;
-  if (group_axes) *group_axes = si < 0 ? -1 : c->geom.sw[si].b - c->geom.sw[si].a;
+  if (group_axes) *group_axes = si < 0 ? -1 : best / 4096 >= SW_SPLIT ? 3 : c->geom.sw[si].b - c->geom.sw[si].a;
   if (mode) *mode = best < 0 ? -1 : best / 4096;
   return MG_OK;
 }
@@ -1507,7 +1679,8 @@ mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double
   if (launches) *launches = best < 0 ? 0 : c->prof[best].first;
   if (total_ms) *total_ms = best < 0 ? 0.0 : best_ms;
   // a moments-only sweep reads the state once; every other sweep reads and writes it
-  if (bytes) *bytes = (best / 4096 == SW_MOMENTS ? 1.0 : 2.0) * (double)c->geom.N_total * (double)c->csize;
+  const int md = best / 4096;
+  if (bytes) *bytes = (md == SW_MOMENTS || md == SW_SPLIT_MOM ? 1.0 : 2.0) * (double)c->geom.N_total * (double)c->csize;
   if (reset) c->prof.clear();
   return MG_OK;
 }

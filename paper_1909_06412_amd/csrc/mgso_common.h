@@ -107,7 +107,7 @@ struct PacketGeom {
   int32_t tab_len;        // sum_l N_l (A and M tables)
   int32_t fast16;         // every axis has 16 points and D >= 3: 16-point sweep kernels
   int32_t gtab_len;       // sum over sweeps of the group sizes (combined tables)
-  int32_t pad1;
+  int32_t split;          // 1: the three-pass plan of 16^8 complex64 grids (tables at gtab_len)
   double hbar;
   AxisDesc ax[MGK_MAXD];
   SweepDesc sw[MGK_MAXD];

@@ -301,7 +301,9 @@ template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, 
   return b > red ? b : red;
 }
 
-enum : int { SW_FULL = 0, SW_MOMENTS = 1, SW_ROUNDTRIP = 2 };
+// Sweep modes (profile classes): SW_SPLIT / SW_SPLIT_MOM are the passes of the
+// three-pass 16^8 plan (the latter reduced to the momentum moments, no store).
+enum : int { SW_FULL = 0, SW_MOMENTS = 1, SW_ROUNDTRIP = 2, SW_SPLIT = 3, SW_SPLIT_MOM = 4 };
 
 // MODE (strided one-axis sweeps only) splits a kinetic substep differently at its
 // turning point, where the last forward sweep meets the first inverse sweep on the

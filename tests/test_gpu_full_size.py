@@ -143,3 +143,34 @@ def test_coupled_16e8_round_trip_returns_initial_gaussian():
     assert moved > 1e-3          # the forward steps did change the state
     assert dq < 1e-6 and dp < 1e-6
     assert e < TOL64
+
+
+def test_three_pass_plan_matches_four_sweep_plan():
+    """Engine 0 runs 16^8 complex64 kinetic substeps in three passes per direction
+    (one axis split into two 4-point digits); engine 2 in the four radix-16 sweeps.
+    Same arithmetic up to rounding: the sampled states and the centres agree."""
+    mg = _mg()
+    w = W.henon_heiles_8d()
+    w["q0"] = [2.0 - 0.15 * l for l in range(8)]
+    w["p0"] = [0.2 * l - 0.7 for l in range(8)]
+    nsteps = 2
+    g1 = O.Grid([16], [w["dq"][0]], w["hbar"])
+    fac = [O.gaussian(g1, [w["q0"][l]], [w["p0"][l]], [w["sigma"][l]]).physical() for l in range(8)]
+    flat, _ = _samples(w, [np.abs(f) ** 2 for f in fac], seed=13)
+    out = []
+    for engine in (0, 2):
+        print(f"[full] coupled 16^8 c64 engine {engine}: {nsteps} steps", flush=True)
+        m = _run_full(w, "c64")
+        try:
+            m.set_option(mg.MG_OPT_ENGINE, engine)
+            m.step(w["dt"], nsteps)
+            out.append((_gpu_samples(m, flat), *m.centres()[:2]))
+        finally:
+            _release(m)
+    (s0, q0, p0), (s2, q2, p2) = out
+    e = float(np.linalg.norm(s0 - s2) / np.linalg.norm(s2))
+    dq = float(np.max(np.abs(q0 - q2)))
+    dp = float(np.max(np.abs(p0 - p2)))
+    print(f"[full] three-pass vs four-sweep: sampled state {e:.3e} dq {dq:.3e} dp {dp:.3e}", flush=True)
+    assert dq < 1e-7 and dp < 1e-7
+    assert e < 1e-6

@@ -293,6 +293,6 @@ def test_generic_engine_on_sixteen_point_grid(precision):
     with pytest.raises(mg.MgError):
         m = mg.from_workload(w, precision=precision)
         try:
-            m.set_option(mg.MG_OPT_ENGINE, 2)
+            m.set_option(mg.MG_OPT_ENGINE, 3)
         finally:
             m.close()
