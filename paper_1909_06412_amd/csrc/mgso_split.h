@@ -41,7 +41,7 @@ constexpr int SPL_NT = 1024;
 constexpr uint32_t SPL_TILE = 16384;
 constexpr uint32_t SPL_TILE_LDS = SPL_TILE + SPL_TILE / 16;  // pad16 gaps
 constexpr int SPL_TAB = 2 * 1024 + 16;                        // split entries appended to AG / MG
-constexpr size_t SPL_LDS_BYTES = (size_t)(SPL_TILE_LDS + 2 * 1024) * sizeof(float2);
+constexpr size_t SPL_LDS_BYTES = (size_t)(SPL_TILE_LDS + 2 * 1024 + 16) * sizeof(float2);
 
 struct SplitDesc {
   int32_t pX, pY, pZ;  // flat bit positions of the in-tile fields X (4 bits), Y (2), Z (4)
@@ -74,6 +74,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   C* lds = reinterpret_cast<C*>(lds_raw);
   C* __restrict__ ltab = lds + SPL_TILE_LDS;
   C* __restrict__ lmt = ltab + 1024;
+  C* __restrict__ lsm = lmt + 1024;  // the 16-entry table (read once per tile)
   const SplitDesc d = a.d;
   const PacketGeom& G = *a.geom;
   const uint64_t off = G.off;
@@ -83,6 +84,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   for (uint32_t i = t; i < 1024u; i += SPL_NT) {
     ltab[i] = a.AG[d.tab + i];
     if (HAS_M) lmt[i] = a.MG[d.tab + i];
+    if (i < 16u) lsm[i] = KIND == SPL_C_RT ? a.MG[d.small + i] : a.AG[d.small + i];
   }
   __syncthreads();
 
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
       // Y lines hold (k0 = j) at fixed n0: undo the twiddle and c(n0), apply M of X and Z
       C s[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) s[j] = a.AG[d.small + 4 * (int)oth + j];
+      for (int j = 0; j < 4; ++j) s[j] = lsm[4 * oth + j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -227,7 +229,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
         // k0 = j: twiddle W16^(n0 k0) and the low digit's A factor c(n0)
         C s[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) s[j] = a.AG[d.small + 4 * (int)oth + j];
+        for (int j = 0; j < 4; ++j) s[j] = lsm[4 * oth + j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -268,7 +270,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
         // M of X and Z and of the split axis at k = k0 + 4 k1, then back
         C m[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) m[j] = a.MG[d.small + (int)oth + 4 * j];
+        for (int j = 0; j < 4; ++j) m[j] = lsm[oth + 4 * j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
