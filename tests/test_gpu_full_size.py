@@ -174,3 +174,37 @@ def test_three_pass_plan_matches_four_sweep_plan():
     print(f"[full] three-pass vs four-sweep: sampled state {e:.3e} dq {dq:.3e} dp {dp:.3e}", flush=True)
     assert dq < 1e-7 and dp < 1e-7
     assert e < 1e-6
+
+
+def test_three_pass_plan_graph_replays_match_eager():
+    """MG_OPT_GRAPH on the 16^8 complex64 grid (the three-pass plan's launches
+    captured once and replayed): every replay equals an eager context fed the same
+    calls bit for bit, with eager work (observables) between the replays."""
+    import torch
+    mg = _mg()
+    w = W.henon_heiles_8d()
+    g1 = O.Grid([16], [w["dq"][0]], w["hbar"])
+    fac = [O.gaussian(g1, [w["q0"][l]], [w["p0"][l]], [w["sigma"][l]]).physical() for l in range(8)]
+    flat, _ = _samples(w, [np.abs(f) ** 2 for f in fac], seed=14)
+    print("[full] graph 16^8 c64: eager and captured contexts", flush=True)
+    a = _run_full(w, "c64")
+    b = _run_full(w, "c64")
+    try:
+        b.set_option(mg.MG_OPT_GRAPH, 1)
+        for rep in range(3):
+            a.step(w["dt"], 1)
+            b.step(w["dt"], 1)          # rep 0 captures, reps 1-2 replay
+            sa, sb = _gpu_samples(a, flat), _gpu_samples(b, flat)
+            qa, pa, ta = a.centres()
+            qb, pb, tb = b.centres()
+            d = float(np.max(np.abs(sa - sb)))
+            print(f"[full] graph 16^8 c64 replay {rep}: max |eager - replay| = {d:.3e}", flush=True)
+            assert d == 0.0
+            assert np.array_equal(qa, qb) and np.array_equal(pa, pb) and ta == tb
+            if rep == 1:
+                oa, ob = a.observables(), b.observables()   # eager work between replays
+                assert oa["norm"] == ob["norm"]
+            torch.cuda.synchronize()
+    finally:
+        _release(a)
+        _release(b)
