@@ -88,9 +88,12 @@ def _run_full(w, precision):
     return mg.from_workload(w, precision=precision)
 
 
-@pytest.mark.parametrize("precision", ["c64", "c128"])
-def test_separable_16e8_matches_product_of_axis_oracles(precision):
+@pytest.mark.parametrize("precision,split,comp,order", [
+    ("c64", "TVT", "suzuki", 4), ("c128", "TVT", "suzuki", 4),
+    ("c64", "VTV", "strang", 2), ("c64", "TVT", "triple_jump", 4)])
+def test_separable_16e8_matches_product_of_axis_oracles(precision, split, comp, order):
     w = W.henon_heiles_8d(lam=0.0)
+    w["split"], w["comp"], w["order"] = split, comp, order
     # distinct axes, so that a transposed axis or a wrong digit order shows
     w["q0"] = [2.0 - 0.15 * l for l in range(8)]
     w["p0"] = [0.2 * l - 0.7 for l in range(8)]
@@ -100,7 +103,7 @@ def test_separable_16e8_matches_product_of_axis_oracles(precision):
     fac = [a.physical() for a in axes]
     flat, dig = _samples(w, [np.abs(f) ** 2 for f in fac], seed=11)
     ref = _product(fac, dig)
-    print(f"[full] separable 16^8 {precision}: {nsteps} steps", flush=True)
+    print(f"[full] separable 16^8 {precision} {split} {comp}{order}: {nsteps} steps", flush=True)
     m = _run_full(w, precision)
     try:
         m.step(w["dt"], nsteps)
@@ -111,7 +114,8 @@ def test_separable_16e8_matches_product_of_axis_oracles(precision):
     e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     dq = max(abs(q[l] - axes[l].q_ctr[0]) for l in range(8))
     dp = max(abs(p[l] - axes[l].p_ctr[0]) for l in range(8))
-    print(f"[full] separable 16^8 {precision}: sampled state {e:.3e} dq {dq:.3e} dp {dp:.3e}", flush=True)
+    print(f"[full] separable 16^8 {precision} {split} {comp}{order}: sampled state {e:.3e} dq {dq:.3e} "
+          f"dp {dp:.3e}", flush=True)
     tc = 1e-12 if precision == "c128" else 1e-6
     assert dq < tc and dp < tc
     assert e < (TOL128 if precision == "c128" else TOL64)
