@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
             } else {
               ang = angM(ax, X) + angM(az, Z);
             }
-          } else {
+          } else if (e < 2064) {
             const int k = e - 2048;
             if (doA) {
               // c(n0) W16^(n0 k0) at 4 n0 + k0
@@ -238,6 +238,11 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
             } else {
               ang = angM(ys, k);
             }
+          } else {
+            // per-axis M of pass C's X and Z axes (its round trip goes axis by axis);
+            // the A side of these entries is unused
+            const int k = (e - 2064) & 15;
+            ang = doA ? 0.0 : angM(SPL_AX[1][e < 2080 ? 0 : 1], k);
           }
           double sn, cs;
           sincos(ang, &sn, &cs);

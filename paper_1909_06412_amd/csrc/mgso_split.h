@@ -19,13 +19,17 @@
 // slower.  Kinetic substep (Sec. II.G.2, Eq. (55)): sweep 0 forward, B forward, C
 // forward reduced to the momentum moments (nothing stored), finalize, C round trip
 // (forward DFTs, the kinetic factor M, inverse DFTs), B inverse, sweep 0 inverse.
+// The round trip goes axis by axis (Z, then X, then the Y digit: M is a product of
+// per-axis factors and DFTs along different axes commute), so it needs the same two
+// LDS transposes as a one-way pass.
 //
 // Tables (built by the finalize kernel at G.gtab_len in AG / MG, 1024 + 1024 + 16
-// entries each): AG[tB + g] = A_X A_Z d(Y) for pass B, with d(n1) the high-digit
-// part of axis 2's A factor (that factor is a linear phase with a sign (-1)^n, so
-// A_2(n0 + 4 n1) = c(n0) d(n1)), AG[tC + g] = A_X A_Z for pass C, AG[tS + 4 n0 +
-// k0] = c(n0) W16^(n0 k0); MG[tB + g] = M_X M_Z, MG[tC + g] = M_X M_Z and MG[tS + k]
-// = M_2(k).  g = X + 16 Y + 64 Z.
+// entries each, then 48): AG[tB + g] = A_X A_Z d(Y) for pass B, with d(n1) the
+// high-digit part of axis 2's A factor (that factor is a linear phase with a sign
+// (-1)^n, so A_2(n0 + 4 n1) = c(n0) d(n1)), AG[tC + g] = A_X A_Z for pass C, AG[tS +
+// 4 n0 + k0] = c(n0) W16^(n0 k0); MG[tB + g] = M_X M_Z of pass B, MG[tS + k] =
+// M_2(k) and, for pass C's per-axis round trips, MG[tS + 16 + k] = M_X(k) and
+// MG[tS + 32 + k] = M_Z(k).  g = X + 16 Y + 64 Z.
 #pragma once
 #include "mgso_sweep16.h"
 
@@ -40,8 +44,8 @@ constexpr int SPL_SPLIT_AXIS = 2;
 constexpr int SPL_NT = 1024;
 constexpr uint32_t SPL_TILE = 16384;
 constexpr uint32_t SPL_TILE_LDS = SPL_TILE + SPL_TILE / 16;  // pad16 gaps
-constexpr int SPL_TAB = 2 * 1024 + 16;                        // split entries appended to AG / MG
-constexpr size_t SPL_LDS_BYTES = (size_t)(SPL_TILE_LDS + 2 * 1024 + 16) * sizeof(float2);
+constexpr int SPL_TAB = 2 * 1024 + 48;                        // split entries appended to AG / MG
+constexpr size_t SPL_LDS_BYTES = (size_t)(SPL_TILE_LDS + 2 * 1024 + 48) * sizeof(float2);
 
 struct SplitDesc {
   int32_t pX, pY, pZ;  // flat bit positions of the in-tile fields X (4 bits), Y (2), Z (4)
@@ -68,13 +72,13 @@ template <int KIND>
 __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   typedef float2 C;
   constexpr bool LOADY = KIND == SPL_B_INV;               // load layout: Y lines, else Z lines
-  constexpr bool HAS_M = KIND == SPL_B_INV || KIND == SPL_C_RT;
-  constexpr bool STORE_Z = KIND == SPL_B_INV || KIND == SPL_C_RT;
+  constexpr bool HAS_M = KIND == SPL_B_INV;
+  constexpr bool STORE_Z = KIND == SPL_B_INV;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   C* __restrict__ ltab = lds + SPL_TILE_LDS;
   C* __restrict__ lmt = ltab + 1024;
-  C* __restrict__ lsm = lmt + 1024;  // the 16-entry table (read once per tile)
+  C* __restrict__ lsm = lmt + 1024;  // the 16-entry table(s) (read once per tile)
   const SplitDesc d = a.d;
   const PacketGeom& G = *a.geom;
   const uint64_t off = G.off;
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   for (uint32_t i = t; i < 1024u; i += SPL_NT) {
     ltab[i] = a.AG[d.tab + i];
     if (HAS_M) lmt[i] = a.MG[d.tab + i];
-    if (i < 16u) lsm[i] = KIND == SPL_C_RT ? a.MG[d.small + i] : a.AG[d.small + i];
+    if (i < 48u) lsm[i] = KIND == SPL_C_RT ? a.MG[d.small + i] : i < 16u ? a.AG[d.small + i] : C{0.f, 0.f};
   }
   __syncthreads();
 
@@ -209,6 +213,48 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
       dft16<float, true>(x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmulc(x[k], ltab[zg + 64u * k]);
+    } else if constexpr (KIND == SPL_C_RT) {
+      // per-axis round trips: A of X and Z, then along Z: DFT, M_Z, inverse DFT; the
+      // X lines the same with M_X; the Y digit with M_2 at k = k0 + 4 k1; conj(A)
+      const C* __restrict__ m2 = lsm;
+      const C* __restrict__ mx = lsm + 16;
+      const C* __restrict__ mz = lsm + 32;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], ltab[zg + 64u * k]);
+      dft16<float, false>(x);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mz[k]);
+      dft16<float, true>(x);
+      z_to_lds(x);
+      __syncthreads();
+      lds_to_x(x);
+      __syncthreads();
+      dft16<float, false>(x);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mx[k]);
+      dft16<float, true>(x);
+      x_to_lds(x);
+      __syncthreads();
+      lds_to_y(x);
+      __syncthreads();
+      C m[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) m[j] = m2[oth + 4 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dft4(&x[4 * i], false);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmul(x[4 * i + j], m[j]);
+        dft4(&x[4 * i], true);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmulc(x[4 * i + j], ltab[yg + 16u * j + 64u * i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) (dst + ybase(base, i, j))[loff] = x[4 * i + j];
     } else {
       // forward half: A factors, DFT along Z, X, then the 4-point Y digit
 #pragma unroll
@@ -265,33 +311,6 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
           if (l != AX && l != AY && l != AZ)
             acc[1 + l] += ws * ((double)((base >> (4 * (7 - l))) & 15u) - 8.0);
         continue;
-      }
-      if constexpr (KIND == SPL_C_RT) {
-        // M of X and Z and of the split axis at k = k0 + 4 k1, then back
-        C m[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) m[j] = lsm[oth + 4 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const C v = cmul(x[4 * i + j], m[j]);
-            x[4 * i + j] = cmul(v, lmt[yg + 16u * j + 64u * i]);
-          }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) dft4(&x[4 * i], true);
-        y_to_lds(x);
-        __syncthreads();
-        lds_to_x(x);
-        __syncthreads();
-        dft16<float, true>(x);
-        x_to_lds(x);
-        __syncthreads();
-        lds_to_z(x);
-        __syncthreads();
-        dft16<float, true>(x);
-#pragma unroll
-        for (int k = 0; k < 16; ++k) x[k] = cmulc(x[k], ltab[zg + 64u * k]);
       }
     }
     if constexpr (STORE_Z) {
