@@ -21,7 +21,9 @@
 // (forward DFTs, the kinetic factor M, inverse DFTs), B inverse, sweep 0 inverse.
 // The round trip goes axis by axis (Z, then X, then the Y digit: M is a product of
 // per-axis factors and DFTs along different axes commute), so it needs the same two
-// LDS transposes as a one-way pass.
+// LDS transposes as a one-way pass.  Every pass loads its tile as Z lines and stores
+// it from Y lines (pass B inverse applies its pointwise factors first and then the
+// inverse DFTs in the order Z, X, Y): loaded as Y lines it took 5% longer.
 //
 // Tables (built by the finalize kernel at G.gtab_len in AG / MG, 1024 + 1024 + 16
 // entries each, then 48): AG[tB + g] = A_X A_Z d(Y) for pass B, with d(n1) the
@@ -71,9 +73,8 @@ struct SplArgs {
 template <int KIND>
 __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   typedef float2 C;
-  constexpr bool LOADY = KIND == SPL_B_INV;               // load layout: Y lines, else Z lines
   constexpr bool HAS_M = KIND == SPL_B_INV;
-  constexpr bool STORE_Z = KIND == SPL_B_INV;
+
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
   C* __restrict__ ltab = lds + SPL_TILE_LDS;
@@ -132,15 +133,8 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   C xn[16];
   auto load = [&](uint32_t tl) {
     const uint32_t base = tile_base(tl);
-    if (LOADY) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xn[4 * i + j] = (src + ybase(base, i, j))[loff];
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) xn[k] = (src + zbase_k(base, k))[loff];
-    }
+    for (int k = 0; k < 16; ++k) xn[k] = (src + zbase_k(base, k))[loff];
   };
   if (blockIdx.x < d.ntiles) load(blockIdx.x);
 
@@ -154,10 +148,6 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) lds[zl + 1088u * k] = x[k];
   };
-  auto lds_to_z = [&](C* x) {
-#pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = lds[zl + 1088u * k];
-  };
   auto x_to_lds = [&](C* x) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) lds[xl + 17u * k] = x[k];
@@ -165,12 +155,6 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
   auto lds_to_x = [&](C* x) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) x[k] = lds[xl + 17u * k];
-  };
-  auto y_to_lds = [&](C* x) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) lds[yl + 272u * j + 1088u * i] = x[4 * i + j];
   };
   auto lds_to_y = [&](C* x) {
 #pragma unroll
@@ -188,31 +172,32 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
     if (tile + gridDim.x < d.ntiles) load(tile + gridDim.x);
 
     if constexpr (KIND == SPL_B_INV) {
-      // Y lines hold (k0 = j) at fixed n0: undo the twiddle and c(n0), apply M of X and Z
-      C s[4];
+      // Z lines as loaded, each at a fixed stored digit k0 = t >> 8: undo the twiddle
+      // and c(n0) and apply M of X and Z (all pointwise), inverse DFTs along Z and X,
+      // then along the Y digit in the Y-line layout, conj(A), store from there
+      const C s0 = lsm[4u * oth + (t >> 8)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) s[j] = lsm[4 * oth + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const C v = cmulc(x[4 * i + j], s[j]);
-          x[4 * i + j] = cmul(v, lmt[yg + 16u * j + 64u * i]);
-        }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) dft4(&x[4 * i], true);
-      y_to_lds(x);
+      for (int k = 0; k < 16; ++k) x[k] = cmul(cmulc(x[k], s0), lmt[zg + 64u * k]);
+      dft16<float, true>(x);
+      z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
       __syncthreads();
       dft16<float, true>(x);
       x_to_lds(x);
       __syncthreads();
-      lds_to_z(x);
+      lds_to_y(x);
       __syncthreads();
-      dft16<float, true>(x);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmulc(x[k], ltab[zg + 64u * k]);
+      for (int i = 0; i < 4; ++i) dft4(&x[4 * i], true);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmulc(x[4 * i + j], ltab[yg + 16u * j + 64u * i]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) (dst + ybase(base, i, j))[loff] = x[4 * i + j];
     } else if constexpr (KIND == SPL_C_RT) {
       // per-axis round trips: A of X and Z, then along Z: DFT, M_Z, inverse DFT; the
       // X lines the same with M_X; the Y digit with M_2 at k = k0 + 4 k1; conj(A)
@@ -313,10 +298,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
         continue;
       }
     }
-    if constexpr (STORE_Z) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) (dst + zbase_k(base, k))[loff] = x[k];
-    } else if constexpr (KIND == SPL_B_FWD) {
+    if constexpr (KIND == SPL_B_FWD) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
