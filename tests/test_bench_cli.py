@@ -1,5 +1,5 @@
 """bench.py's command line on a host without a GPU run: more than one GPU is
-refused with a message (this build measures one GPU), before any device work."""
+refused with a message (the benchmark measures one GPU), before any device work."""
 import os
 import subprocess
 import sys
@@ -13,3 +13,22 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_kernel_labels_of_profile_classes():
+    """The kernel name bench.py looks up in the traffic summary for each profiled
+    class (sweep, dir, epi, group axes, mode), as rocprofv3 prints it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    w = W.henon_heiles_8d()
+    assert bench.kernel_label(w, "c64", (0, 1, 4, 3, 0)) == "k_sweep16<float, 3, true, 4, 3, 0>"
+    assert bench.kernel_label(w, "c64", (0, 0, 0, 3, 0)) == "k_sweep16<float, 3, false, 0, -1, 0>"
+    assert bench.kernel_label(w, "c128", (3, 0, 1, 1, 1)) == "k_sweep16<double, 1, false, 1, -1, 1>"
+    # the three-pass plan: pass B forward / inverse, pass C moments-only / round trip
+    assert bench.kernel_label(w, "c64", (1, 0, 0, 3, 3)) == "k_split<0>"
+    assert bench.kernel_label(w, "c64", (1, 1, 0, 3, 3)) == "k_split<1>"
+    assert bench.kernel_label(w, "c64", (2, 0, 1, 3, 4)) == "k_split<2>"
+    assert bench.kernel_label(w, "c64", (2, 1, 0, 3, 3)) == "k_split<3>"
+    small = W.harmonic_3d()
+    assert bench.kernel_label(small, "c128", (0, 0, 1, 3, 0)) == "k_sweep<double>"
