@@ -112,7 +112,7 @@ def kernel_label(w, precision, cls):
     t = "float" if precision == "c64" else "double"
     if mode >= 3:
         # passes of the three-pass 16^8 plan: B forward 0, B inverse 1, C moments 2, C round trip 3
-        return f"k_split<{2 if mode == 4 else (d if si == 1 else 3)}>"
+        return f"k_split<{t}, {2 if mode == 4 else (d if si == 1 else 3)}>"
     fast16 = w["D"] >= 3 and all(n == 16 for n in w["N"]) and w["potential"][0] != "morse_repulsion"
     if not fast16:
         return f"k_sweep<{t}>"

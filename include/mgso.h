@@ -84,8 +84,8 @@ typedef enum {
 typedef enum {
   MG_OPT_ENGINE = 1,         /* sweep kernels of a single grid: 0 = automatic (the radix-16
                                 register kernels when D >= 3 and every axis has 16
-                                points, with the three-pass plan for 16^8 complex64
-                                grids; else the Stockham LDS sweeps), 1 = the Stockham
+                                points, with the three-pass plan for 16^8 grids;
+                                else the Stockham LDS sweeps), 1 = the Stockham
                                 LDS sweeps for every grid, 2 = the radix-16 kernels
                                 without the three-pass plan                               */
   MG_OPT_GRAPH = 2,          /* 1 = capture the launches of mg_step / mg_batch_step once

@@ -215,19 +215,17 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
         for (int e = threadIdx.x; e < SPL_TAB; e += NTHR) {
           double ang, mag = 1.0;
           if (e < 2048) {
+            // A products of the passes (the kinetic factors go per axis below)
+            if (!doA) continue;
             const int pass = e >> 10, g = e & 1023;
             const int X = g & 15, Y = (g >> 4) & 3, Z = g >> 6;
             const int ax = SPL_AX[pass][0], az = SPL_AX[pass][1];
-            if (doA) {
-              ang = angA(ax, X) + angA(az, Z);
-              mag = 1.0 / 16.0;
-              if (pass == 0) {
-                // high digit n1 = Y of the split axis: its index 4 n1 is even
-                ang -= st.p_c[ys] * (double)(4 * Y) * G.ax[ys].dq / hbar;
-                mag = 1.0 / 64.0;
-              }
-            } else {
-              ang = angM(ax, X) + angM(az, Z);
+            ang = angA(ax, X) + angA(az, Z);
+            mag = 1.0 / 16.0;
+            if (pass == 0) {
+              // high digit n1 = Y of the split axis: its index 4 n1 is even
+              ang -= st.p_c[ys] * (double)(4 * Y) * G.ax[ys].dq / hbar;
+              mag = 1.0 / 64.0;
             }
           } else if (e < 2064) {
             const int k = e - 2048;
@@ -239,10 +237,9 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
               ang = angM(ys, k);
             }
           } else {
-            // per-axis M of pass C's X and Z axes (its round trip goes axis by axis);
-            // the A side of these entries is unused
-            const int k = (e - 2064) & 15;
-            ang = doA ? 0.0 : angM(SPL_AX[1][e < 2080 ? 0 : 1], k);
+            // per-axis M: pass C's X and Z axes, then pass B's (the A side is unused)
+            const int q = (e - 2064) >> 4, k = (e - 2064) & 15;
+            ang = doA ? 0.0 : angM(SPL_AX[q < 2 ? 1 : 0][q & 1], k);
           }
           double sn, cs;
           sincos(ang, &sn, &cs);
@@ -846,22 +843,23 @@ template <typename T> static mg_status launch_pointwise(mg_ctx* c, int epi, doub
 
 // Forward transform of src into dst (dst may equal src); the last sweep reduces
 // the momentum moments with epilogue `epi_last`.
-// The three-pass plan runs a 16^8 complex64 step's kinetic substeps (engine 0).
+// The three-pass plan runs a 16^8 step's kinetic substeps (engine 0).
 static bool split_step(const mg_ctx* c) { return c->opt_engine == 0 && c->geom.split && fast16_turn(c); }
 
-template <int KIND> static void launch_split_k(mg_ctx* c, const SplArgs& a, int grid) {
-  hipLaunchKernelGGL(k_split<KIND>, dim3(grid), dim3(SPL_NT), SPL_LDS_BYTES, c->stream, a);
+template <typename T, int KIND> static void launch_split_k(mg_ctx* c, const SplArgs<T>& a, int grid) {
+  hipLaunchKernelGGL((k_split<T, KIND>), dim3(grid), dim3(spl_nt<T>()), spl_lds_bytes<T>(), c->stream, a);
 }
 
 // One pass of the three-pass plan on buf (in place); kind SPL_*.  One workgroup
 // per compute unit (the tile takes most of the LDS), each looping over its tiles.
-static mg_status launch_split(mg_ctx* c, int kind, void* buf, int* nblk) {
-  SplArgs a;
+template <typename T> static mg_status launch_split(mg_ctx* c, int kind, void* buf, int* nblk) {
+  typedef typename CT<T>::type C;
+  SplArgs<T> a;
   a.geom = c->d_geom;
-  a.src = (const float2*)buf;
-  a.dst = (float2*)buf;
-  a.AG = (const float2*)c->d_AG;
-  a.MG = (const float2*)c->d_MG;
+  a.src = (const C*)buf;
+  a.dst = (C*)buf;
+  a.AG = (const C*)c->d_AG;
+  a.MG = (const C*)c->d_MG;
   a.partials = c->d_part;
   a.d = c->spl[kind >= SPL_C_MOM ? 1 : 0];
   const int grid = std::min<int>(c->n_cu > 0 ? c->n_cu : 256, MAX_BLOCKS);
@@ -873,10 +871,10 @@ static mg_status launch_split(mg_ctx* c, int kind, void* buf, int* nblk) {
     HIPCHK(c, hipEventRecord(pe.e0, c->stream));
   }
   switch (kind) {
-    case SPL_B_FWD: launch_split_k<SPL_B_FWD>(c, a, grid); break;
-    case SPL_B_INV: launch_split_k<SPL_B_INV>(c, a, grid); break;
-    case SPL_C_MOM: launch_split_k<SPL_C_MOM>(c, a, grid); break;
-    default: launch_split_k<SPL_C_RT>(c, a, grid); break;
+    case SPL_B_FWD: launch_split_k<T, SPL_B_FWD>(c, a, grid); break;
+    case SPL_B_INV: launch_split_k<T, SPL_B_INV>(c, a, grid); break;
+    case SPL_C_MOM: launch_split_k<T, SPL_C_MOM>(c, a, grid); break;
+    default: launch_split_k<T, SPL_C_RT>(c, a, grid); break;
   }
   HIPCHK(c, hipGetLastError());
   if (c->opt_profile) {
@@ -900,8 +898,8 @@ static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int ep
     if (epi_last != EPI_REDP) return fail(c, MG_EINVAL, "internal: the three-pass plan reduces momentum moments");
     int nb;
     mg_status r = launch_sweep<T>(c, 0, DIR_FWD, 0, 0.0, src, dst, &nb, fast);
-    if (!r) r = launch_split(c, SPL_B_FWD, dst, &nb);
-    if (!r) r = launch_split(c, SPL_C_MOM, dst, nblk_last);
+    if (!r) r = launch_split<T>(c, SPL_B_FWD, dst, &nb);
+    if (!r) r = launch_split<T>(c, SPL_C_MOM, dst, nblk_last);
     return r;
   }
   for (int s = 0; s < ns; ++s) {
@@ -921,8 +919,8 @@ static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, do
   const int ns = c->geom.nsweeps;
   if (fast && turn && split_step(c)) {
     int nb;
-    mg_status r = launch_split(c, SPL_C_RT, buf, &nb);
-    if (!r) r = launch_split(c, SPL_B_INV, buf, &nb);
+    mg_status r = launch_split<T>(c, SPL_C_RT, buf, &nb);
+    if (!r) r = launch_split<T>(c, SPL_B_INV, buf, &nb);
     if (!r) r = launch_sweep<T>(c, 0, DIR_INV, epi_first_sweep, hV, buf, buf, nblk_last, fast);
     return r;
   }
@@ -1114,15 +1112,13 @@ template <typename T> static hipError_t set_lds_attr16() {
   return e;
 }
 
-static hipError_t set_lds_attr_split() {
-  const int b = (int)SPL_LDS_BYTES;
-  hipError_t e = hipFuncSetAttribute((const void*)k_split<SPL_B_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_split<SPL_B_INV>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_split<SPL_C_MOM>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_split<SPL_C_RT>, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+template <typename T> static hipError_t set_lds_attr_split() {
+  const int b = (int)spl_lds_bytes<T>();
+  const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+  hipError_t e = hipFuncSetAttribute((const void*)k_split<T, SPL_B_FWD>, at, b);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_split<T, SPL_B_INV>, at, b);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_split<T, SPL_C_MOM>, at, b);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k_split<T, SPL_C_RT>, at, b);
   return e;
 }
 
@@ -1176,12 +1172,13 @@ static void setup_fast16(mg_ctx* c) {
   G.fast16 = 1;
 }
 
-// The three-pass plan of 16^8 complex64 grids (mgso_split.h): the radix-16 plan
-// must be sweep 0 over axes 5-7 (contiguous tile) and three strided sweeps.
+// The three-pass plan of 16^8 grids (mgso_split.h): the radix-16 plan must be
+// sweep 0 over axes 5-7 (contiguous tile) and three strided sweeps.
 static void setup_split(mg_ctx* c) {
   PacketGeom& G = c->geom;
   G.split = 0;
-  if (!G.fast16 || c->prec != MG_C64 || G.D != 8 || G.nsweeps != 4) return;
+  if (!G.fast16 || G.D != 8 || G.nsweeps != 4) return;
+  const int lr = c->prec == MG_C64 ? spl_lr<float>() : spl_lr<double>();  // log2 of the run
   if (c->s16[0].K != 3 || c->s16[0].a != 5 || c->s16[0].kind != 0) return;
   const int p2 = 4 * (7 - SPL_SPLIT_AXIS);
   for (int p = 0; p < 2; ++p) {
@@ -1194,8 +1191,8 @@ static void setup_split(mg_ctx* c) {
     d.pZ = 4 * (7 - d.axZ);
     d.pY = p == 0 ? p2 + 2 : p2;
     d.pYc = p == 0 ? p2 : p2 + 2;
-    const uint32_t in = 0xFu | (0xFu << d.pX) | (0x3u << d.pY) | (0xFu << d.pZ);
-    // the tile index fills the other 18 bits: maximal runs of them, low first
+    const uint32_t in = ((1u << lr) - 1u) | (0xFu << d.pX) | (0x3u << d.pY) | (0xFu << d.pZ);
+    // the tile index fills the other bits: maximal runs of them, low first
     int nf = 0, nb = 0;
     for (int b = 0; b < 32;) {
       if ((in >> b) & 1u) {
@@ -1211,9 +1208,9 @@ static void setup_split(mg_ctx* c) {
       nb += w;
       b += w;
     }
-    if (nb != 18 || __builtin_popcount(in) != 14) return;
+    if (nb != 22 - lr || __builtin_popcount(in) != 10 + lr) return;
     d.nf = nf;
-    d.ntiles = 1u << 18;
+    d.ntiles = 1u << (22 - lr);
     d.tab = G.gtab_len + 1024 * p;
     d.small = G.gtab_len + 2048;
   }
@@ -1294,7 +1291,8 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
     where = "hipFuncSetAttribute";
     e = prec == MG_C128 ? set_lds_attr16<double>() : set_lds_attr16<float>();
   }
-  if (e == hipSuccess && c->geom.split) e = set_lds_attr_split();
+  if (e == hipSuccess && c->geom.split)
+    e = prec == MG_C128 ? set_lds_attr_split<double>() : set_lds_attr_split<float>();
   if (e == hipSuccess && c->geom.split) {
     int dev = 0;
     e = hipGetDevice(&dev);

@@ -1,9 +1,10 @@
-// mgso_split.h -- three-pass transforms of 16^8 complex64 grids.
+// mgso_split.h -- three-pass transforms of 16^8 grids.
 //
 // The radix-16 plan of a 16^8 grid takes four passes per transform direction:
 // axes 5-7 (a contiguous 4096-point tile), then 3-4, 1-2 and 0 (strided tiles).
-// A strided tile can hold 16384 complex64 points (128 KiB of LDS); with runs of 16
-// consecutive points that leaves 10 transform bits per tile, and 12 + 10 + 10
+// A strided tile can hold 16384 complex64 points or 8192 complex128 points (128
+// KiB of LDS); with runs of 128 bytes (16 or 8 consecutive points) that leaves 10
+// transform bits per tile, and 12 + 10 + 10
 // covers the 32 bits of the grid in three passes once one axis (axis 2) is split
 // into two 4-point digits, n = n0 + 4 n1.  A 16-point DFT is a 4-point DFT over
 // the high digit n1 (giving k0), the twiddle W16^(n0 k0), and a 4-point DFT over
@@ -14,7 +15,8 @@
 //           axis 0 (Z, bits 28-31)
 //   pass C: axis 4 (X, bits 12-15), the low digit of axis 2 (Y, bits 20-21),
 //           axis 1 (Z, bits 24-27)
-// (run: bits 0-3, axis 7).  Each pass pairs a middle axis with an outer one: tiles
+// (run: bits 0-3, complex128 bits 0-2, of axis 7).  Each pass pairs a middle axis with
+// an outer one: tiles
 // whose transform bits all sit in the top bits of the address measured a quarter
 // slower.  Kinetic substep (Sec. II.G.2, Eq. (55)): sweep 0 forward, B forward, C
 // forward reduced to the momentum moments (nothing stored), finalize, C round trip
@@ -25,13 +27,13 @@
 // it from Y lines (pass B inverse applies its pointwise factors first and then the
 // inverse DFTs in the order Z, X, Y): loaded as Y lines it took 5% longer.
 //
-// Tables (built by the finalize kernel at G.gtab_len in AG / MG, 1024 + 1024 + 16
-// entries each, then 48): AG[tB + g] = A_X A_Z d(Y) for pass B, with d(n1) the
-// high-digit part of axis 2's A factor (that factor is a linear phase with a sign
-// (-1)^n, so A_2(n0 + 4 n1) = c(n0) d(n1)), AG[tC + g] = A_X A_Z for pass C, AG[tS +
-// 4 n0 + k0] = c(n0) W16^(n0 k0); MG[tB + g] = M_X M_Z of pass B, MG[tS + k] =
-// M_2(k) and, for pass C's per-axis round trips, MG[tS + 16 + k] = M_X(k) and
-// MG[tS + 32 + k] = M_Z(k).  g = X + 16 Y + 64 Z.
+// Tables (built by the finalize kernel at G.gtab_len in AG / MG: 1024 + 1024 + 80
+// entries each): AG[tB + g] = A_X A_Z d(Y) for pass B, with d(n1) the high-digit
+// part of axis 2's A factor (that factor is a linear phase with a sign (-1)^n, so
+// A_2(n0 + 4 n1) = c(n0) d(n1)), AG[tC + g] = A_X A_Z for pass C, AG[tS + 4 n0 + k0] =
+// c(n0) W16^(n0 k0); per-axis kinetic factors MG[tS + k] = M_2(k), MG[tS + 16 + k]
+// and MG[tS + 32 + k] = M of pass C's X and Z axes, MG[tS + 48 + k] and MG[tS + 64 +
+// k] = M of pass B's X and Z axes.  g = X + 16 Y + 64 Z.
 #pragma once
 #include "mgso_sweep16.h"
 
@@ -43,11 +45,18 @@ enum : int { SPL_B_FWD = 0, SPL_B_INV = 1, SPL_C_MOM = 2, SPL_C_RT = 3 };
 // and one digit of axis SPL_SPLIT_AXIS (p = 0: the high digit, p = 1: the low one).
 constexpr int SPL_AX[2][2] = {{3, 0}, {4, 1}};
 constexpr int SPL_SPLIT_AXIS = 2;
-constexpr int SPL_NT = 1024;
-constexpr uint32_t SPL_TILE = 16384;
-constexpr uint32_t SPL_TILE_LDS = SPL_TILE + SPL_TILE / 16;  // pad16 gaps
-constexpr int SPL_TAB = 2 * 1024 + 48;                        // split entries appended to AG / MG
-constexpr size_t SPL_LDS_BYTES = (size_t)(SPL_TILE_LDS + 2 * 1024 + 48) * sizeof(float2);
+// Tile geometry: a run of R = 2^LR consecutive points (128 bytes), 1024 R points,
+// 64 R threads with 16 points each.
+template <typename T> constexpr int spl_lr() { return sizeof(T) == 4 ? 4 : 3; }
+template <typename T> constexpr int spl_nt() { return 64 << spl_lr<T>(); }
+template <typename T> constexpr uint32_t spl_tile_lds() {
+  return (1024u << spl_lr<T>()) + (64u << spl_lr<T>());  // the tile and its pad16 gaps
+}
+constexpr int SPL_SMALL = 80;                 // 16-entry tables: twiddles or M_2, then four per-axis M
+constexpr int SPL_TAB = 2 * 1024 + SPL_SMALL;  // split entries appended to AG / MG
+template <typename T> constexpr size_t spl_lds_bytes() {
+  return (size_t)(spl_tile_lds<T>() + 1024 + SPL_SMALL) * 2 * sizeof(T);
+}
 
 struct SplitDesc {
   int32_t pX, pY, pZ;  // flat bit positions of the in-tile fields X (4 bits), Y (2), Z (4)
@@ -57,60 +66,61 @@ struct SplitDesc {
   int32_t flo[4], fw[4];
   uint32_t ntiles;
   int32_t tab;         // this pass's 1024-entry tables in AG / MG
-  int32_t small;       // the 16-entry table (AG for pass B, MG for pass C)
+  int32_t small;       // the 16-entry tables (tS)
 };
 
-struct SplArgs {
+template <typename T> struct SplArgs {
   const PacketGeom* geom;
-  const float2* src;
-  float2* dst;
-  const float2* AG;
-  const float2* MG;
+  const typename CT<T>::type* src;
+  typename CT<T>::type* dst;
+  const typename CT<T>::type* AG;
+  const typename CT<T>::type* MG;
   double* partials;
   SplitDesc d;
 };
 
-template <int KIND>
-__global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
-  typedef float2 C;
-  constexpr bool HAS_M = KIND == SPL_B_INV;
+template <typename T, int KIND>
+__global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
+  typedef typename CT<T>::type C;
+  constexpr int LR = spl_lr<T>(), R = 1 << LR, NT = spl_nt<T>();
 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
-  C* __restrict__ ltab = lds + SPL_TILE_LDS;
-  C* __restrict__ lmt = ltab + 1024;
-  C* __restrict__ lsm = lmt + 1024;  // the 16-entry table(s) (read once per tile)
+  C* __restrict__ ltab = lds + spl_tile_lds<T>();
+  C* __restrict__ lsm = ltab + 1024;  // the 16-entry tables (read once per tile)
   const SplitDesc d = a.d;
   const PacketGeom& G = *a.geom;
   const uint64_t off = G.off;
   const C* __restrict__ src = a.src + off;
   C* __restrict__ dst = a.dst + off;
   const uint32_t t = threadIdx.x;
-  for (uint32_t i = t; i < 1024u; i += SPL_NT) {
+  for (uint32_t i = t; i < 1024u; i += NT) {
     ltab[i] = a.AG[d.tab + i];
-    if (HAS_M) lmt[i] = a.MG[d.tab + i];
-    if (i < 48u) lsm[i] = KIND == SPL_C_RT ? a.MG[d.small + i] : i < 16u ? a.AG[d.small + i] : C{0.f, 0.f};
+    if (i < (uint32_t)SPL_SMALL) lsm[i] = (i < 16u && KIND != SPL_C_RT) ? a.AG[d.small + i] : a.MG[d.small + i];
   }
   __syncthreads();
 
-  const uint32_t run = t & 15u;
-  // In the Z- and Y-line layouts a lane's (run, X) = (t & 15, (t >> 4) & 15) and
-  // the rest of its position, t >> 8, is the same across a wave (64 lanes): HBM
-  // addresses are a wave-uniform base plus a 32-bit lane offset.
-  const uint32_t lX = (t >> 4) & 15u;
-  const uint32_t w8 = __builtin_amdgcn_readfirstlane(t >> 8);
+  // Tile index u = run + R X + 16 R Y + 64 R Z.  In the Z- and Y-line layouts a
+  // lane's (run, X) = (t & (R-1), (t >> LR) & 15) and the rest of its position,
+  // t >> (LR+4), is the same across a wave (64 lanes): HBM addresses are a
+  // wave-uniform base plus a 32-bit lane offset.
+  const uint32_t run = t & (uint32_t)(R - 1);
+  const uint32_t lX = (t >> LR) & 15u;
+  const uint32_t wY = t >> (LR + 4);
+  const uint32_t wYs = __builtin_amdgcn_readfirstlane(wY);
   const uint32_t loff = run | (lX << d.pX);
-  // Z lines: thread (run, X, Y = t >> 8), point k at Z = k
-  const uint32_t zbase = w8 << d.pY;
-  const uint32_t zg = lX + 16u * (t >> 8);  // + 64 k
-  // X lines: thread (run, Y, Z), point k at X = k
-  const uint32_t xY = (t >> 4) & 3u, xZ = t >> 6;
-  const uint32_t xl = pad16(run + 256u * xY + 1024u * xZ);  // + 17 k
-  // Y lines: thread (run, X, Zb + i), Zb = 4 (t >> 8), point 4 i + j at Y = j
-  const uint32_t yZb = 4u * w8;
-  const uint32_t yl = pad16(run + 16u * lX + 1024u * (4u * (t >> 8)));  // + 272 j + 1088 i
-  const uint32_t yg = lX + 64u * (4u * (t >> 8));                    // + 16 j + 64 i
-  const uint32_t zl = pad16(t);                                       // + 1088 k
+  // Z lines: thread (run, X, Y = wY), point k at Z = k: u = t + NT k
+  const uint32_t zbase = wYs << d.pY;
+  const uint32_t zg = lX + 16u * wY;  // + 64 k
+  const uint32_t zl = pad16(t);       // + (NT + NT/16) k
+  // X lines: thread (run, Y, Z), point k at X = k (pad16 of u + R k is pad16(u) + R k +
+  // (R k >> 4), as run + R (k mod (16/R)) stays below 16)
+  const uint32_t xY = (t >> LR) & 3u, xZ = t >> (LR + 2);
+  const uint32_t xl = pad16(run + 16u * R * xY + 64u * R * xZ);
+  // Y lines: thread (run, X, Zb + i), Zb = 4 wY, point 4 i + j at Y = j
+  const uint32_t yZb = 4u * wYs;
+  const uint32_t yl = pad16(run + R * lX + 256u * R * wY);  // + 17 R j + 68 R i
+  const uint32_t yg = lX + 256u * wY;                       // + 16 j + 64 i
 
   auto tile_base = [&](uint32_t tl) -> uint32_t {
     uint32_t b = 0, sh = 0;
@@ -144,23 +154,24 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
 
   // LDS moves between the three line layouts (each followed by a barrier pair)
   // (pad16 of u + 16 m is pad16(u) + 17 m when u's low four bits stay below 16)
+  constexpr uint32_t ZS = NT + NT / 16;
   auto z_to_lds = [&](C* x) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lds[zl + 1088u * k] = x[k];
+    for (int k = 0; k < 16; ++k) lds[zl + ZS * k] = x[k];
   };
   auto x_to_lds = [&](C* x) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) lds[xl + 17u * k] = x[k];
+    for (int k = 0; k < 16; ++k) lds[xl + R * k + ((R * k) >> 4)] = x[k];
   };
   auto lds_to_x = [&](C* x) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) x[k] = lds[xl + 17u * k];
+    for (int k = 0; k < 16; ++k) x[k] = lds[xl + R * k + ((R * k) >> 4)];
   };
   auto lds_to_y = [&](C* x) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) x[4 * i + j] = lds[yl + 272u * j + 1088u * i];
+      for (int j = 0; j < 4; ++j) x[4 * i + j] = lds[yl + 17u * R * j + 68u * R * i];
   };
 
   for (uint32_t tile = blockIdx.x; tile < d.ntiles; tile += gridDim.x) {
@@ -172,18 +183,18 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
     if (tile + gridDim.x < d.ntiles) load(tile + gridDim.x);
 
     if constexpr (KIND == SPL_B_INV) {
-      // Z lines as loaded, each at a fixed stored digit k0 = t >> 8: undo the twiddle
-      // and c(n0) and apply M of X and Z (all pointwise), inverse DFTs along Z and X,
-      // then along the Y digit in the Y-line layout, conj(A), store from there
-      const C s0 = lsm[4u * oth + (t >> 8)];
+      // Z lines as loaded, each at a fixed stored digit k0 = wY: undo the twiddle and
+      // c(n0) and apply M of X and Z (all pointwise), inverse DFTs along Z and X, then
+      // along the Y digit in the Y-line layout, conj(A), store from there
+      const C sx = cmulc(lsm[48u + lX], lsm[4u * oth + wY]);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(cmulc(x[k], s0), lmt[zg + 64u * k]);
-      dft16<float, true>(x);
+      for (int k = 0; k < 16; ++k) x[k] = cmul(cmul(x[k], sx), lsm[64 + k]);
+      dft16<T, true>(x);
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
       __syncthreads();
-      dft16<float, true>(x);
+      dft16<T, true>(x);
       x_to_lds(x);
       __syncthreads();
       lds_to_y(x);
@@ -206,18 +217,18 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
       const C* __restrict__ mz = lsm + 32;
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], ltab[zg + 64u * k]);
-      dft16<float, false>(x);
+      dft16<T, false>(x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mz[k]);
-      dft16<float, true>(x);
+      dft16<T, true>(x);
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
       __syncthreads();
-      dft16<float, false>(x);
+      dft16<T, false>(x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mx[k]);
-      dft16<float, true>(x);
+      dft16<T, true>(x);
       x_to_lds(x);
       __syncthreads();
       lds_to_y(x);
@@ -244,12 +255,12 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
       // forward half: A factors, DFT along Z, X, then the 4-point Y digit
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], ltab[zg + 64u * k]);
-      dft16<float, false>(x);
+      dft16<T, false>(x);
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
       __syncthreads();
-      dft16<float, false>(x);
+      dft16<T, false>(x);
       x_to_lds(x);
       __syncthreads();
       lds_to_y(x);
@@ -282,7 +293,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
         constexpr int AX = SPL_AX[1][0], AZ = SPL_AX[1][1], AY = SPL_SPLIT_AXIS;
         const double ws = (wi[0] + wi[1]) + (wi[2] + wi[3]);
         acc[0] += ws;
-        acc[1 + 7] += ws * ((double)run - 8.0);
+        acc[1 + 7] += ws * ((double)(run | (base & 15u)) - 8.0);  // axis 7: the run and (complex128) bit 3
         acc[1 + AX] += ws * ((double)lX - 8.0);
         double mz = 0.0, my = 0.0;
 #pragma unroll
@@ -306,7 +317,7 @@ __global__ __launch_bounds__(SPL_NT) void k_split(SplArgs a) {
     }
   }
   if constexpr (KIND == SPL_C_MOM)
-    block_reduce<SPL_NT>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
+    block_reduce<NT>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
 }
 
 }  // namespace mgk

@@ -26,9 +26,10 @@ def test_kernel_labels_of_profile_classes():
     assert bench.kernel_label(w, "c64", (0, 0, 0, 3, 0)) == "k_sweep16<float, 3, false, 0, -1, 0>"
     assert bench.kernel_label(w, "c128", (3, 0, 1, 1, 1)) == "k_sweep16<double, 1, false, 1, -1, 1>"
     # the three-pass plan: pass B forward / inverse, pass C moments-only / round trip
-    assert bench.kernel_label(w, "c64", (1, 0, 0, 3, 3)) == "k_split<0>"
-    assert bench.kernel_label(w, "c64", (1, 1, 0, 3, 3)) == "k_split<1>"
-    assert bench.kernel_label(w, "c64", (2, 0, 1, 3, 4)) == "k_split<2>"
-    assert bench.kernel_label(w, "c64", (2, 1, 0, 3, 3)) == "k_split<3>"
+    assert bench.kernel_label(w, "c64", (1, 0, 0, 3, 3)) == "k_split<float, 0>"
+    assert bench.kernel_label(w, "c64", (1, 1, 0, 3, 3)) == "k_split<float, 1>"
+    assert bench.kernel_label(w, "c64", (2, 0, 1, 3, 4)) == "k_split<float, 2>"
+    assert bench.kernel_label(w, "c64", (2, 1, 0, 3, 3)) == "k_split<float, 3>"
+    assert bench.kernel_label(w, "c128", (2, 1, 0, 3, 3)) == "k_split<double, 3>"
     small = W.harmonic_3d()
     assert bench.kernel_label(small, "c128", (0, 0, 1, 3, 0)) == "k_sweep<double>"

@@ -149,10 +149,11 @@ def test_coupled_16e8_round_trip_returns_initial_gaussian():
     assert e < TOL64
 
 
-def test_three_pass_plan_matches_four_sweep_plan():
-    """Engine 0 runs 16^8 complex64 kinetic substeps in three passes per direction
-    (one axis split into two 4-point digits); engine 2 in the four radix-16 sweeps.
-    Same arithmetic up to rounding: the sampled states and the centres agree."""
+@pytest.mark.parametrize("precision", ["c64", "c128"])
+def test_three_pass_plan_matches_four_sweep_plan(precision):
+    """Engine 0 runs 16^8 kinetic substeps in three passes per direction (one axis
+    split into two 4-point digits); engine 2 in the four radix-16 sweeps.  Same
+    arithmetic up to rounding: the sampled states and the centres agree."""
     mg = _mg()
     w = W.henon_heiles_8d()
     w["q0"] = [2.0 - 0.15 * l for l in range(8)]
@@ -163,8 +164,8 @@ def test_three_pass_plan_matches_four_sweep_plan():
     flat, _ = _samples(w, [np.abs(f) ** 2 for f in fac], seed=13)
     out = []
     for engine in (0, 2):
-        print(f"[full] coupled 16^8 c64 engine {engine}: {nsteps} steps", flush=True)
-        m = _run_full(w, "c64")
+        print(f"[full] coupled 16^8 {precision} engine {engine}: {nsteps} steps", flush=True)
+        m = _run_full(w, precision)
         try:
             m.set_option(mg.MG_OPT_ENGINE, engine)
             m.step(w["dt"], nsteps)
@@ -175,9 +176,11 @@ def test_three_pass_plan_matches_four_sweep_plan():
     e = float(np.linalg.norm(s0 - s2) / np.linalg.norm(s2))
     dq = float(np.max(np.abs(q0 - q2)))
     dp = float(np.max(np.abs(p0 - p2)))
-    print(f"[full] three-pass vs four-sweep: sampled state {e:.3e} dq {dq:.3e} dp {dp:.3e}", flush=True)
-    assert dq < 1e-7 and dp < 1e-7
-    assert e < 1e-6
+    print(f"[full] three-pass vs four-sweep {precision}: sampled state {e:.3e} dq {dq:.3e} dp {dp:.3e}",
+          flush=True)
+    tol = (1e-7, 1e-6) if precision == "c64" else (1e-13, 1e-12)
+    assert dq < tol[0] and dp < tol[0]
+    assert e < tol[1]
 
 
 def test_three_pass_plan_graph_replays_match_eager():
