@@ -44,15 +44,23 @@ def run_objective(workload: dict, params: dict, nsteps: int, R_d: float, w: floa
 
 
 def fd_gradient(workload: dict, names, nsteps: int, R_d: float, w: float, rel=1e-4):
-    """Central differences of J with respect to the named potential parameters."""
+    """Central differences of J with respect to the named potential parameters.  A name
+    is a scalar parameter ("A") or an entry of an array parameter (("k", 0))."""
     _, base = workload["potential"]
     out = []
     for nm in names:
-        hstep = rel * max(abs(base[nm]), 1.0)
-        plus = dict(base)
-        minus = dict(base)
-        plus[nm] = base[nm] + hstep
-        minus[nm] = base[nm] - hstep
-        out.append((run_objective(workload, plus, nsteps, R_d, w)
-                    - run_objective(workload, minus, nsteps, R_d, w)) / (2 * hstep))
+        key, idx = (nm, None) if isinstance(nm, str) else nm
+        value = base[key] if idx is None else base[key][idx]
+        hstep = rel * max(abs(value), 1.0)
+        moved = []
+        for sign in (1.0, -1.0):
+            par = dict(base)
+            if idx is None:
+                par[key] = value + sign * hstep
+            else:
+                arr = list(base[key])
+                arr[idx] = value + sign * hstep
+                par[key] = arr
+            moved.append(run_objective(workload, par, nsteps, R_d, w))
+        out.append((moved[0] - moved[1]) / (2 * hstep))
     return np.array(out)
