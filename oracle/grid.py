@@ -15,7 +15,7 @@ below count the paper's displayed equations in order of appearance.
 
 The transforms here follow the paper literally: f = N^(-1/2) exp(-2 pi i <K,J>)
 exp(-i t_KJ / hbar), with t_KJ split into its J-only, K-only and constant parts,
-and the DFT done by numpy's FFT (library primitive).  The brute-force matrices at
+and the DFT done by scipy's FFT (library primitive).  The brute-force matrices at
 the bottom build the same objects element by element for tiny grids.
 """
 from __future__ import annotations
@@ -23,6 +23,17 @@ from __future__ import annotations
 import itertools
 
 import numpy as np
+import scipy.fft
+
+# Threads of the FFT library primitive (scipy.fft's `workers`); 1 unless a caller
+# (a large test, the all-core CPU baseline) asks for more.  The arithmetic does not
+# depend on it.
+FFT_WORKERS = 1
+
+
+def set_fft_workers(n: int) -> None:
+    global FFT_WORKERS
+    FFT_WORKERS = max(1, int(n))
 
 
 class Grid:
@@ -100,7 +111,7 @@ class Grid:
         u = psi.astype(np.complex128, copy=True)
         for al in a:
             u = u * al
-        x = np.fft.fftn(u, norm="ortho")          # N^(-1/2) sum_J exp(-2 pi i <K,J>) u_J
+        x = scipy.fft.fftn(u, norm="ortho", workers=FFT_WORKERS)   # N^(-1/2) sum_J exp(-2 pi i <K,J>) u_J
         for bl in b:
             x = x * bl
         return const * x
@@ -111,7 +122,7 @@ class Grid:
         x = psit.astype(np.complex128, copy=True)
         for bl in b:
             x = x * np.conj(bl)
-        u = np.fft.ifftn(x, norm="ortho")         # N^(-1/2) sum_K exp(+2 pi i <J,K>) x_K
+        u = scipy.fft.ifftn(x, norm="ortho", workers=FFT_WORKERS)  # N^(-1/2) sum_K exp(+2 pi i <J,K>) x_K
         for al in a:
             u = u * np.conj(al)
         return np.conj(const) * u

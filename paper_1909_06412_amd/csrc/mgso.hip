@@ -110,10 +110,10 @@ template <typename T> struct FinArgs {
   int mode;
   double h;
   double forced[MGK_MAXD];
-  typename CT<T>::type* A;
-  typename CT<T>::type* M;
-  typename CT<T>::type* AG;   // group-combined tables (16-point path), may be null
-  typename CT<T>::type* MG;
+  typename TE<T>::type* A;
+  typename TE<T>::type* M;
+  typename TE<T>::type* AG;   // group-combined tables (16-point path), may be null
+  typename TE<T>::type* MG;
 };
 
 template <typename T>
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
           }
           double s, c;
           sincos(ang, &s, &c);
-          C v = C{(decltype(C().x))(mag * c), (decltype(C().x))(mag * s)};
+          const typename TE<T>::type v = make_te<T>(mag * c, mag * s);
           if (doA) a.AG[sw.gtab_off + g] = v;
           else a.MG[sw.gtab_off + g] = v;
         }
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
           }
           double sn, cs;
           sincos(ang, &sn, &cs);
-          const C v = C{(decltype(C().x))(mag * cs), (decltype(C().x))(mag * sn)};
+          const typename TE<T>::type v = make_te<T>(mag * cs, mag * sn);
           if (doA) a.AG[G.gtab_len + e] = v;
           else a.MG[G.gtab_len + e] = v;
         }
@@ -654,14 +654,16 @@ static mg_status fail(mg_ctx* c, mg_status s, const std::string& msg) {
       return fail((ctx), MG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
-template <typename T> static void build_twiddles(const std::map<int, int>& offs, int total, std::vector<T>& out) {
-  out.assign(2 * (size_t)total, (T)0);
+// Twiddle table of each axis length n: exp(-2 pi i m / n) for m < n at off + m, as
+// table entries (make_te: complex64 keeps the remainder of the rounding as well).
+template <typename T> static void build_twiddles(const std::map<int, int>& offs, int total,
+                                                 std::vector<typename mgk::TE<T>::type>& out) {
+  out.assign((size_t)total, mgk::make_te<T>(0.0, 0.0));
   for (auto& kv : offs) {
     const int n = kv.first, off = kv.second;
     for (int m = 0; m < n; ++m) {
       const long double ang = -2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)n;
-      out[2 * (off + m)] = (T)cosl(ang);
-      out[2 * (off + m) + 1] = (T)sinl(ang);
+      out[off + m] = mgk::make_te<T>((double)cosl(ang), (double)sinl(ang));
     }
   }
 }
@@ -672,8 +674,8 @@ static int grid_for(uint64_t work_items) {
 }
 
 template <typename T> static Tables<T> tables_of(mg_ctx* c) {
-  typedef typename CT<T>::type C;
-  return Tables<T>{(const C*)c->d_tw, (const C*)c->d_A, (const C*)c->d_M};
+  typedef typename TE<T>::type E;
+  return Tables<T>{(const E*)c->d_tw, (const E*)c->d_A, (const E*)c->d_M};
 }
 
 template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, double h, int nblk, const double* forced) {
@@ -688,10 +690,11 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
   a.h = h;
   if (forced)
     for (int l = 0; l < c->D; ++l) a.forced[l] = forced[l];
-  a.A = (C*)c->d_A;
-  a.M = (C*)c->d_M;
-  a.AG = (C*)c->d_AG;
-  a.MG = (C*)c->d_MG;
+  typedef typename TE<T>::type E;
+  a.A = (E*)c->d_A;
+  a.M = (E*)c->d_M;
+  a.AG = (E*)c->d_AG;
+  a.MG = (E*)c->d_MG;
   hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(NTHR), 0, c->stream, a);
   HIPCHK(c, hipGetLastError());
   return MG_OK;
@@ -764,8 +767,8 @@ static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, con
     a.pot = c->d_pot;
     a.src = (const C*)src;
     a.dst = (C*)dst;
-    a.AG = (const C*)c->d_AG;
-    a.MG = (const C*)c->d_MG;
+    a.AG = (const typename TE<T>::type*)c->d_AG;
+    a.MG = (const typename TE<T>::type*)c->d_MG;
     a.partials = c->d_part;
     a.d = c->s16[si];
     a.h = h;
@@ -858,8 +861,8 @@ template <typename T> static mg_status launch_split(mg_ctx* c, int kind, void* b
   a.geom = c->d_geom;
   a.src = (const C*)buf;
   a.dst = (C*)buf;
-  a.AG = (const C*)c->d_AG;
-  a.MG = (const C*)c->d_MG;
+  a.AG = (const typename TE<T>::type*)c->d_AG;
+  a.MG = (const typename TE<T>::type*)c->d_MG;
   a.partials = c->d_part;
   a.d = c->spl[kind >= SPL_C_MOM ? 1 : 0];
   const int grid = std::min<int>(c->n_cu > 0 ? c->n_cu : 256, MAX_BLOCKS);
@@ -1280,13 +1283,14 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   e = hipMalloc(&c->d_geom, sizeof(PacketGeom));
   if (e == hipSuccess) e = hipMalloc(&c->d_st, sizeof(PacketState));
   if (e == hipSuccess) e = hipMalloc(&c->d_pot, sizeof(PotDesc));
-  if (e == hipSuccess) e = hipMalloc(&c->d_tw, (size_t)tw_total * c->csize);
-  if (e == hipSuccess) e = hipMalloc(&c->d_A, (size_t)c->geom.tab_len * c->csize);
-  if (e == hipSuccess) e = hipMalloc(&c->d_M, (size_t)c->geom.tab_len * c->csize);
+  // table entries are 16 bytes in both precisions (make_te)
+  if (e == hipSuccess) e = hipMalloc(&c->d_tw, (size_t)tw_total * 16);
+  if (e == hipSuccess) e = hipMalloc(&c->d_A, (size_t)c->geom.tab_len * 16);
+  if (e == hipSuccess) e = hipMalloc(&c->d_M, (size_t)c->geom.tab_len * 16);
   if (e == hipSuccess) e = hipMalloc(&c->d_part, (size_t)MAX_BLOCKS * MGK_NACC * sizeof(double));
   const size_t gtab = (size_t)c->geom.gtab_len + (c->geom.split ? SPL_TAB : 0);
-  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, gtab * c->csize);
-  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, gtab * c->csize);
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_AG, gtab * 16);
+  if (e == hipSuccess && c->geom.fast16) e = hipMalloc(&c->d_MG, gtab * 16);
   if (e == hipSuccess && c->geom.fast16) {
     where = "hipFuncSetAttribute";
     e = prec == MG_C128 ? set_lds_attr16<double>() : set_lds_attr16<float>();
@@ -1304,13 +1308,13 @@ mg_status mg_create(int D, const int32_t* N, const double* dq, const double* inv
   if (e == hipSuccess) e = hipMemset(c->d_st, 0, sizeof(PacketState));
   if (e == hipSuccess) {
     if (prec == MG_C64) {
-      std::vector<float> tw;
+      std::vector<float4> tw;
       build_twiddles<float>(tw_offs, tw_total, tw);
-      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(float4), hipMemcpyHostToDevice);
     } else {
-      std::vector<double> tw;
+      std::vector<double2> tw;
       build_twiddles<double>(tw_offs, tw_total, tw);
-      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double), hipMemcpyHostToDevice);
+      e = hipMemcpy(c->d_tw, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice);
     }
   }
   if (e != hipSuccess) {

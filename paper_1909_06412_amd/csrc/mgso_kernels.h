@@ -69,6 +69,90 @@ template <typename C> __device__ __forceinline__ C rot(C a, bool inv) {
   return inv ? C{-a.y, a.x} : C{a.y, -a.x};
 }
 
+// Multiplication by a real constant k of the DFTs.  complex64: k is carried as
+// hi + lo (hi = k rounded to FP32, lo = the FP32 rounding of what is left), so the
+// product is k x rounded once.  With k alone rounded to FP32, every root of unity
+// (c, s) built from rounded constants has c^2 + s^2 != 1 by a few 1e-8, always with
+// the same sign: a 16-point DFT then loses 2.3e-8 of the norm on average, every
+// transform of every step, which adds up to a steady norm decay (norm preservation,
+// Sec. II.G, is the property the moving grid must keep).  complex128: plain product.
+template <typename T> __device__ __forceinline__ T kmul(T x, double k);
+template <> __device__ __forceinline__ float kmul<float>(float x, double k) {
+  const float hi = (float)k, lo = (float)(k - (double)hi);
+  return __builtin_fmaf(x, hi, x * lo);
+}
+template <> __device__ __forceinline__ double kmul<double>(double x, double k) { return x * k; }
+
+// v * (c + i s) with c, s given in FP64; complex64 as hi + lo pairs (see kmul).
+template <typename T, typename C> __device__ __forceinline__ C crotk(C v, double c, double s) {
+  if constexpr (sizeof(T) == 4) {
+    const float ch = (float)c, cl = (float)(c - (double)ch);
+    const float sh = (float)s, sl = (float)(s - (double)sh);
+    const float tr = __builtin_fmaf(-v.y, sl, v.x * cl);
+    const float ti = __builtin_fmaf(v.y, cl, v.x * sl);
+    return C{__builtin_fmaf(v.x, ch, __builtin_fmaf(-v.y, sh, tr)),
+             __builtin_fmaf(v.y, ch, __builtin_fmaf(v.x, sh, ti))};
+  } else {
+    return C{v.x * c - v.y * s, v.x * s + v.y * c};
+  }
+}
+
+// Twiddle of a table: v * w (or v * conj(w) when conj) with w = hi, plus its
+// complex64 remainder lo (the table stores both, see the twiddle tables' layout).
+template <typename T, typename C> __device__ __forceinline__ C cmul_tw(C v, C w, C wl, bool conj) {
+  if constexpr (sizeof(T) == 4) {
+    const float wy = conj ? -w.y : w.y, ly = conj ? -wl.y : wl.y;
+    const float tr = __builtin_fmaf(-v.y, ly, v.x * wl.x);
+    const float ti = __builtin_fmaf(v.y, wl.x, v.x * ly);
+    return C{__builtin_fmaf(v.x, w.x, __builtin_fmaf(-v.y, wy, tr)),
+             __builtin_fmaf(v.y, w.x, __builtin_fmaf(v.x, wy, ti))};
+  } else {
+    return conj ? cmulc(v, w) : cmul(v, w);
+  }
+}
+
+// Table entries (twiddles, the per-axis and group phase tables): a root of unity
+// or phase factor computed in FP64 and rounded to the storage precision.  complex64
+// entries are float4 {hi.x, hi.y, lo.x, lo.y}: the rounded value and the rounded
+// remainder, multiplied in with cmul_tw.  A complex64 table entry rounded once has
+// |w|^2 - 1 of about 3e-8, fixed for as long as the table stays; a packet only a few
+// grid points wide weights a handful of entries per axis, so these errors do not
+// average out, and every substep would scale the norm by a random 1e-7 or so.
+// complex128 entries are the plain double2 value.
+template <typename T> struct TE;
+template <> struct TE<float> { typedef float4 type; };
+template <> struct TE<double> { typedef double2 type; };
+
+template <typename T> __host__ __device__ __forceinline__ typename TE<T>::type make_te(double c, double s);
+template <> __host__ __device__ __forceinline__ float4 make_te<float>(double c, double s) {
+  const float ch = (float)c, sh = (float)s;
+  return float4{ch, sh, (float)(c - (double)ch), (float)(s - (double)sh)};
+}
+template <> __host__ __device__ __forceinline__ double2 make_te<double>(double c, double s) {
+  return double2{c, s};
+}
+// The FP64 value of an entry (hi + lo).
+__device__ __forceinline__ double2 te_value(float4 e) {
+  return double2{(double)e.x + (double)e.z, (double)e.y + (double)e.w};
+}
+__device__ __forceinline__ double2 te_value(double2 e) { return e; }
+
+// v * e (or v * conj(e))
+template <typename T, typename C> __device__ __forceinline__ C tmul(C v, typename TE<T>::type e, bool conj = false) {
+  if constexpr (sizeof(T) == 4) {
+    return cmul_tw<T>(v, C{e.x, e.y}, C{e.z, e.w}, conj);
+  } else {
+    return conj ? cmulc(v, e) : cmul(v, e);
+  }
+}
+// The entry a * b (or a * conj(b)), formed in FP64 and rounded once.
+template <typename T> __device__ __forceinline__ typename TE<T>::type te_prod(typename TE<T>::type a,
+                                                                            typename TE<T>::type b, bool conjb) {
+  const double2 x = te_value(a), y = te_value(b);
+  const double yi = conjb ? -y.y : y.y;
+  return make_te<T>(x.x * y.x - x.y * yi, x.x * yi + x.y * y.x);
+}
+
 // ---------------------------------------------------------------------------
 // Small DFTs in registers: forward sign exp(-2 pi i nk/R), inverse exp(+...)
 // ---------------------------------------------------------------------------
@@ -88,7 +172,7 @@ template <typename C> __device__ __forceinline__ void dft4(C* v, bool inv) {
 }
 
 template <typename T, typename C> __device__ __forceinline__ void dft8(C* v, bool inv) {
-  const T h = (T)0.70710678118654752440084436210485;
+  const double h = 0.70710678118654752440084436210485;
   C b[4], c[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
@@ -98,10 +182,12 @@ template <typename T, typename C> __device__ __forceinline__ void dft8(C* v, boo
   // c_n *= w8^n, w8 = exp(-+ i pi / 4)
   {
     C x = c[1];
-    c[1] = inv ? C{h * (x.x - x.y), h * (x.x + x.y)} : C{h * (x.x + x.y), h * (x.y - x.x)};
+    const T d = x.x - x.y, e = x.x + x.y;
+    c[1] = inv ? C{kmul<T>(d, h), kmul<T>(e, h)} : C{kmul<T>(e, h), kmul<T>(-d, h)};
     c[2] = rot(c[2], inv);
     x = c[3];
-    c[3] = inv ? C{-h * (x.x + x.y), h * (x.x - x.y)} : C{h * (x.y - x.x), -h * (x.x + x.y)};
+    const T f = x.x + x.y, g = x.x - x.y;
+    c[3] = inv ? C{kmul<T>(-f, h), kmul<T>(g, h)} : C{kmul<T>(-g, h), kmul<T>(-f, h)};
   }
   dft4(b, inv);
   dft4(c, inv);
@@ -113,29 +199,29 @@ template <typename T, typename C> __device__ __forceinline__ void dft8(C* v, boo
 }
 
 template <typename T, typename C> __device__ __forceinline__ void dft3(C* v, bool inv) {
-  const T s = (T)0.86602540378443864676372317075294;  // sin(2 pi / 3)
+  const double s = 0.86602540378443864676372317075294;  // sin(2 pi / 3)
   C t = cadd(v[1], v[2]);
   C u = csub(v[1], v[2]);
   C y0 = cadd(v[0], t);
   C m = C{v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y};
-  C su = rot(C{s * u.x, s * u.y}, inv);  // -+ i s u
+  C su = rot(C{kmul<T>(u.x, s), kmul<T>(u.y, s)}, inv);  // -+ i s u
   v[0] = y0;
   v[1] = cadd(m, su);
   v[2] = csub(m, su);
 }
 
 template <typename T, typename C> __device__ __forceinline__ void dft5(C* v, bool inv) {
-  const T c1 = (T)0.30901699437494742410229341718282;   // cos(2 pi / 5)
-  const T c2 = (T)-0.80901699437494742410229341718282;  // cos(4 pi / 5)
-  const T s1 = (T)0.95105651629515357211643933337938;   // sin(2 pi / 5)
-  const T s2 = (T)0.58778525229247312916870595463907;   // sin(4 pi / 5)
+  const double c1 = 0.30901699437494742410229341718282;   // cos(2 pi / 5)
+  const double c2 = -0.80901699437494742410229341718282;  // cos(4 pi / 5)
+  const double s1 = 0.95105651629515357211643933337938;   // sin(2 pi / 5)
+  const double s2 = 0.58778525229247312916870595463907;   // sin(4 pi / 5)
   C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
   C u1 = csub(v[1], v[4]), u2 = csub(v[2], v[3]);
   C y0 = C{v[0].x + t1.x + t2.x, v[0].y + t1.y + t2.y};
-  C m1 = C{v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y};
-  C m2 = C{v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y};
-  C n1 = rot(C{s1 * u1.x + s2 * u2.x, s1 * u1.y + s2 * u2.y}, inv);
-  C n2 = rot(C{s2 * u1.x - s1 * u2.x, s2 * u1.y - s1 * u2.y}, inv);
+  C m1 = C{v[0].x + kmul<T>(t1.x, c1) + kmul<T>(t2.x, c2), v[0].y + kmul<T>(t1.y, c1) + kmul<T>(t2.y, c2)};
+  C m2 = C{v[0].x + kmul<T>(t1.x, c2) + kmul<T>(t2.x, c1), v[0].y + kmul<T>(t1.y, c2) + kmul<T>(t2.y, c1)};
+  C n1 = rot(C{kmul<T>(u1.x, s1) + kmul<T>(u2.x, s2), kmul<T>(u1.y, s1) + kmul<T>(u2.y, s2)}, inv);
+  C n2 = rot(C{kmul<T>(u1.x, s2) - kmul<T>(u2.x, s1), kmul<T>(u1.y, s2) - kmul<T>(u2.y, s1)}, inv);
   v[0] = y0;
   v[1] = cadd(m1, n1);
   v[4] = csub(m1, n1);
@@ -186,9 +272,8 @@ template <typename T, int A, int B, typename C> __device__ __forceinline__ void 
       C x = u[k1];
       const int m = (b * k1) % R;
       if (m != 0) {
-        const T c = (T)Unity<R>::c[m], sn = (T)Unity<R>::s[m];
         // forward w = c - i sn, inverse w = c + i sn
-        x = inv ? C{x.x * c - x.y * sn, x.x * sn + x.y * c} : C{x.x * c + x.y * sn, x.y * c - x.x * sn};
+        x = crotk<T>(x, Unity<R>::c[m], inv ? Unity<R>::s[m] : -Unity<R>::s[m]);
       }
       t[b * A + k1] = x;
     }
@@ -226,9 +311,9 @@ template <typename T, int R, typename C> __device__ __forceinline__ void dftR(C*
 template <typename T, int R, int NTHR, int TM = MGK_TMAX>
 __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_t Tn, uint32_t n,
                                               uint32_t S, Div32 dS, const PassDesc& pd, bool inv,
-                                              const typename CT<T>::type* __restrict__ tw,
-                                              const typename CT<T>::type* __restrict__ pre,
-                                              const typename CT<T>::type* __restrict__ post,
+                                              const typename TE<T>::type* __restrict__ tw,
+                                              const typename TE<T>::type* __restrict__ pre,
+                                              const typename TE<T>::type* __restrict__ post,
                                               bool post_conj) {
   typedef typename CT<T>::type C;
   constexpr int MB = (TM + R * NTHR - 1) / (R * NTHR);
@@ -249,15 +334,14 @@ __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_
       for (int r = 0; r < R; ++r) v[m][r] = lds[b0 + (j + r * nbl) * S];
       if (pre) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[m][r] = cmul(v[m][r], pre[j + r * nbl]);
+        for (int r = 0; r < R; ++r) v[m][r] = tmul<T>(v[m][r], pre[j + r * nbl]);
       }
       if (Ns > 1) {
         const uint32_t k = j - div32(j, pd.dNs) * Ns;
         const uint32_t step = k * pd.tws;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          C w = tw[r * step];
-          v[m][r] = inv ? cmulc(v[m][r], w) : cmul(v[m][r], w);
+          v[m][r] = tmul<T>(v[m][r], tw[r * step], inv);
         }
       }
       dftR<T, R>(v[m], inv);
@@ -275,7 +359,7 @@ __device__ __forceinline__ void stockham_pass(typename CT<T>::type* lds, uint32_
       for (int r = 0; r < R; ++r) {
         const uint32_t p = o0 + r * Ns;
         C x = v[m][r];
-        if (post) x = post_conj ? cmulc(x, post[p]) : cmul(x, post[p]);
+        if (post) x = tmul<T>(x, post[p], post_conj);
         lds[base[m] + p * S] = x;
       }
     }
@@ -290,9 +374,9 @@ template <typename T, int R, int NTHR>
 __device__ __forceinline__ void stockham_pass_pp(const typename CT<T>::type* __restrict__ in,
                                                  typename CT<T>::type* __restrict__ out, uint32_t Tn, uint32_t n,
                                                  uint32_t S, Div32 dS, const PassDesc& pd, bool inv,
-                                                 const typename CT<T>::type* __restrict__ tw,
-                                                 const typename CT<T>::type* __restrict__ pre,
-                                                 const typename CT<T>::type* __restrict__ post, bool post_conj) {
+                                                 const typename TE<T>::type* __restrict__ tw,
+                                                 const typename TE<T>::type* __restrict__ pre,
+                                                 const typename TE<T>::type* __restrict__ post, bool post_conj) {
   typedef typename CT<T>::type C;
   const uint32_t nbl = n / R;
   const uint32_t nb = Tn / R;
@@ -305,15 +389,14 @@ __device__ __forceinline__ void stockham_pass_pp(const typename CT<T>::type* __r
     for (int r = 0; r < R; ++r) v[r] = in[b0 + (j + r * nbl) * S];
     if (pre) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = cmul(v[r], pre[j + r * nbl]);
+      for (int r = 0; r < R; ++r) v[r] = tmul<T>(v[r], pre[j + r * nbl]);
     }
     const uint32_t k = j - div32(j, pd.dNs) * Ns;
     if (Ns > 1) {
       const uint32_t step = k * pd.tws;
 #pragma unroll
       for (int r = 1; r < R; ++r) {
-        C w = tw[r * step];
-        v[r] = inv ? cmulc(v[r], w) : cmul(v[r], w);
+        v[r] = tmul<T>(v[r], tw[r * step], inv);
       }
     }
     dftR<T, R>(v, inv);
@@ -322,7 +405,7 @@ __device__ __forceinline__ void stockham_pass_pp(const typename CT<T>::type* __r
     for (int r = 0; r < R; ++r) {
       const uint32_t p = o0 + r * Ns;
       C x = v[r];
-      if (post) x = post_conj ? cmulc(x, post[p]) : cmul(x, post[p]);
+      if (post) x = tmul<T>(x, post[p], post_conj);
       out[b0 + p * S] = x;
     }
   }
@@ -336,13 +419,13 @@ __device__ __forceinline__ void stockham_pass_pp(const typename CT<T>::type* __r
 template <typename T, int NTHR>
 __device__ __forceinline__ void tile_axis_fft_pp(typename CT<T>::type* a, typename CT<T>::type* b, int* cur,
                                                  uint32_t Tn, const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
-                                                 const typename CT<T>::type* tw, const typename CT<T>::type* pre,
-                                                 const typename CT<T>::type* post, bool post_conj) {
+                                                 const typename TE<T>::type* tw, const typename TE<T>::type* pre,
+                                                 const typename TE<T>::type* post, bool post_conj) {
   const int np = ax.npass;
   for (int p = 0; p < np; ++p) {
     const PassDesc& pd = ax.pass[p];
-    const typename CT<T>::type* pr = p == 0 ? pre : nullptr;
-    const typename CT<T>::type* po = p == np - 1 ? post : nullptr;
+    const typename TE<T>::type* pr = p == 0 ? pre : nullptr;
+    const typename TE<T>::type* po = p == np - 1 ? post : nullptr;
     typename CT<T>::type* src = *cur ? b : a;
     typename CT<T>::type* dst = *cur ? a : b;
     switch (pd.R) {
@@ -366,14 +449,14 @@ __device__ __forceinline__ void tile_axis_fft_pp(typename CT<T>::type* a, typena
 template <typename T, int NTHR, int TM = MGK_TMAX, bool WIDE = false>
 __device__ __forceinline__ void tile_axis_fft(typename CT<T>::type* lds, uint32_t Tn,
                                               const AxisDesc& ax, uint32_t S, Div32 dS, bool inv,
-                                              const typename CT<T>::type* tw,
-                                              const typename CT<T>::type* pre,
-                                              const typename CT<T>::type* post, bool post_conj) {
+                                              const typename TE<T>::type* tw,
+                                              const typename TE<T>::type* pre,
+                                              const typename TE<T>::type* post, bool post_conj) {
   const int np = ax.npass;
   for (int p = 0; p < np; ++p) {
     const PassDesc& pd = ax.pass[p];
-    const typename CT<T>::type* pr = p == 0 ? pre : nullptr;
-    const typename CT<T>::type* po = p == np - 1 ? post : nullptr;
+    const typename TE<T>::type* pr = p == 0 ? pre : nullptr;
+    const typename TE<T>::type* po = p == np - 1 ? post : nullptr;
     switch (pd.R) {
       case 2: stockham_pass<T, 2, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
       case 3: stockham_pass<T, 3, NTHR, TM>(lds, Tn, ax.n, S, dS, pd, inv, tw, pr, po, post_conj); break;
@@ -548,12 +631,20 @@ __device__ __forceinline__ double pot_dtheta(const PotDesc& P, int D, const doub
   return 0.0;
 }
 
-// exp(-i phi) for the complex64 path without branches: quadrant reduction in FP64
+// x exp(-i phi) for the complex64 path without branches: quadrant reduction in FP64
 // (n = rint(2 phi / pi), r = phi - n pi/2 with pi/2 split in two parts so that the
-// reduction error stays near 1e-16 for |phi| < 1e6), then the Taylor series of
-// sin and cos to x^9 / x^8 in FP32 (truncation below 3e-9 on |r| <= pi/4), then
-// rotation by the quadrant.
-__device__ __forceinline__ float2 phase_poly(double phi) {
+// reduction error stays near 1e-16 for |phi| < 1e6), sin r and cm = cos r - 1 by
+// their Taylor series (sin to r^9, cos to r^10) in FP32 with explicit FMAs, then
+// x (1 + cm) - i x sin r with the 1 kept exact inside the FMAs, then the quarter
+// turns (-i)^n as exact swaps and sign flips.  Keeping cos r as 1 + cm makes the
+// factor unitary to ~r^2 1e-7: cos r rounded to FP32 near 1 would instead leave
+// |exp(-i r)|^2 - 1 = r^2 exactly for every |r| < 2.4e-4 (cos r rounds to 1), a
+// steady norm gain wherever the potential phase is small.  On |r| <= pi/4 the
+// truncation is below 2e-9 (sin) and 1.2e-10 (cos), the FP32 evaluation error about
+// 5e-8; the x^4 coefficient of cos is 1/24 rounded up (one FP32 step above the
+// nearest value), which makes the mean of |factor|^2 - 1 over the reduced range
+// +8e-11 instead of -3.7e-10.
+__device__ __forceinline__ float2 mul_phase_f32(float2 v, double phi) {
   const double two_over_pi = 0.63661977236758134307553505349006;
   // pi/2 split so that n * pio2_hi is exact (32-bit mantissa) (Cody-Waite)
   const double pio2_hi = 1.5707963267341256;
@@ -561,24 +652,33 @@ __device__ __forceinline__ float2 phase_poly(double phi) {
   const double n = rint(phi * two_over_pi);
   const float r = (float)((phi - n * pio2_hi) - n * pio2_lo);
   const float r2 = r * r;
-  const float sn = r * (1.0f + r2 * (-1.0f / 6 + r2 * (1.0f / 120 + r2 * (-1.0f / 5040 + r2 * (1.0f / 362880)))));
-  const float cs = 1.0f + r2 * (-0.5f + r2 * (1.0f / 24 + r2 * (-1.0f / 720 + r2 * (1.0f / 40320))));
+  // sin r = r + r^3 (-1/6 + r^2 (1/120 + r^2 (-1/5040 + r^2 / 362880)))
+  float ps = __builtin_fmaf(r2, 1.0f / 362880.0f, -1.0f / 5040.0f);
+  ps = __builtin_fmaf(ps, r2, 1.0f / 120.0f);
+  ps = __builtin_fmaf(ps, r2, -1.0f / 6.0f);
+  const float sn = __builtin_fmaf(r, r2 * ps, r);
+  // cos r - 1 = r^2 (-1/2 + r^2 (1/24 + r^2 (-1/720 + r^2 (1/40320 - r^2 / 3628800))))
+  float pc = __builtin_fmaf(r2, -1.0f / 3628800.0f, 1.0f / 40320.0f);
+  pc = __builtin_fmaf(pc, r2, -1.0f / 720.0f);
+  pc = __builtin_fmaf(pc, r2, 0x1.555558p-5f);  // 1/24, one FP32 step up
+  pc = __builtin_fmaf(pc, r2, -0.5f);
+  const float cm = r2 * pc;
+  // v exp(-i r) = (x (1 + cm) + y sn, y (1 + cm) - x sn)
+  const float a = __builtin_fmaf(v.y, sn, __builtin_fmaf(v.x, cm, v.x));
+  const float b = __builtin_fmaf(-v.x, sn, __builtin_fmaf(v.y, cm, v.y));
+  // times (-i)^q: q = 1 maps (a, b) to (b, -a), q = 2 to (-a, -b), q = 3 to (-b, a)
   const int q = (int)n & 3;
-  // exp(i phi) = exp(i q pi/2) (cs + i sn): quadrant q swaps the pair when odd and
-  // negates cos for q = 1, 2 and sin for q = 2, 3 (selects and sign flips, no branches)
   const bool odd = (q & 1) != 0;
-  const float c0 = odd ? sn : cs, s0 = odd ? cs : sn;
-  const uint32_t sc = (uint32_t)((q + 1) & 2) << 30, ss = (uint32_t)(q & 2) << 30;
-  const float c = __uint_as_float(__float_as_uint(c0) ^ sc);
-  const float ms = __uint_as_float(__float_as_uint(s0) ^ ss ^ 0x80000000u);  // -sin
-  return float2{c, ms};
+  const float u = odd ? b : a, w = odd ? a : b;
+  const uint32_t su = (uint32_t)(q & 2) << 30, sw = (uint32_t)((q + 1) & 2) << 30;
+  return float2{__uint_as_float(__float_as_uint(u) ^ su), __uint_as_float(__float_as_uint(w) ^ sw)};
 }
 
 // The same in FP64 for the complex128 path: Taylor series to x^17 / x^16 on
 // |r| <= pi/4 (truncation below 1e-19).
 __device__ __forceinline__ double2 phase_poly64(double phi) {
   const double two_over_pi = 0.63661977236758134307553505349006;
-  const double pio2_hi = 1.5707963267341256;   // as in phase_poly
+  const double pio2_hi = 1.5707963267341256;   // as in mul_phase_f32
   const double pio2_lo = 6.077100506506192e-11;
   const double n = rint(phi * two_over_pi);
   const double r = (phi - n * pio2_hi) - n * pio2_lo;
@@ -601,19 +701,16 @@ __device__ __forceinline__ double2 phase_poly64(double phi) {
   return double2{c, -s};
 }
 
-// exp(-i phi) with phi in FP64, rounded to the storage precision.
-template <typename T> __device__ __forceinline__ typename CT<T>::type phase_of(double phi);
-template <> __device__ __forceinline__ float2 phase_of<float>(double phi) {
-  const double two_pi = 6.283185307179586476925286766559;
-  const double r = phi - two_pi * rint(phi * (1.0 / two_pi));
-  float s, c;
-  sincosf((float)r, &s, &c);
-  return float2{c, -s};
-}
-template <> __device__ __forceinline__ double2 phase_of<double>(double phi) {
-  double s, c;
-  sincos(phi, &s, &c);
-  return double2{c, -s};
+// x exp(-i phi) with phi in FP64: complex64 through mul_phase_f32, complex128 with
+// the FP64 sine and cosine.
+template <typename T, typename C> __device__ __forceinline__ C mul_phase(C v, double phi) {
+  if constexpr (sizeof(T) == 4) {
+    return mul_phase_f32(v, phi);
+  } else {
+    double s, c;
+    sincos(phi, &s, &c);
+    return cmul(v, C{c, -s});
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -740,7 +837,7 @@ __device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::t
 #pragma unroll
     for (int l = 0; l < MGK_MAXD; ++l)
       if (l < D) acc[1 + l] += w * g[l];
-    x = cmul(x, phase_of<T>(h * V / G.hbar));
+    x = mul_phase<T>(x, h * V / G.hbar);
   }
   return x;
 }

@@ -55,7 +55,8 @@ template <typename T> constexpr uint32_t spl_tile_lds() {
 constexpr int SPL_SMALL = 80;                 // 16-entry tables: twiddles or M_2, then four per-axis M
 constexpr int SPL_TAB = 2 * 1024 + SPL_SMALL;  // split entries appended to AG / MG
 template <typename T> constexpr size_t spl_lds_bytes() {
-  return (size_t)(spl_tile_lds<T>() + 1024 + SPL_SMALL) * 2 * sizeof(T);
+  // the tile in complex elements, then the tables in 16-byte table entries
+  return (size_t)spl_tile_lds<T>() * 2 * sizeof(T) + (size_t)(1024 + SPL_SMALL) * 16;
 }
 
 struct SplitDesc {
@@ -73,8 +74,8 @@ template <typename T> struct SplArgs {
   const PacketGeom* geom;
   const typename CT<T>::type* src;
   typename CT<T>::type* dst;
-  const typename CT<T>::type* AG;
-  const typename CT<T>::type* MG;
+  const typename TE<T>::type* AG;
+  const typename TE<T>::type* MG;
   double* partials;
   SplitDesc d;
 };
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
 
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
-  C* __restrict__ ltab = lds + spl_tile_lds<T>();
-  C* __restrict__ lsm = ltab + 1024;  // the 16-entry tables (read once per tile)
+  typedef typename TE<T>::type E;
+  E* __restrict__ ltab = reinterpret_cast<E*>(lds + spl_tile_lds<T>());
+  E* __restrict__ lsm = ltab + 1024;  // the 16-entry tables (read once per tile)
   const SplitDesc d = a.d;
   const PacketGeom& G = *a.geom;
   const uint64_t off = G.off;
@@ -186,9 +188,9 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       // Z lines as loaded, each at a fixed stored digit k0 = wY: undo the twiddle and
       // c(n0) and apply M of X and Z (all pointwise), inverse DFTs along Z and X, then
       // along the Y digit in the Y-line layout, conj(A), store from there
-      const C sx = cmulc(lsm[48u + lX], lsm[4u * oth + wY]);
+      const E sx = te_prod<T>(lsm[48u + lX], lsm[4u * oth + wY], true);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(cmul(x[k], sx), lsm[64 + k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(tmul<T>(x[k], sx), lsm[64 + k]);
       dft16<T, true>(x);
       z_to_lds(x);
       __syncthreads();
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmulc(x[4 * i + j], ltab[yg + 16u * j + 64u * i]);
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], ltab[yg + 16u * j + 64u * i], true);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -212,14 +214,14 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
     } else if constexpr (KIND == SPL_C_RT) {
       // per-axis round trips: A of X and Z, then along Z: DFT, M_Z, inverse DFT; the
       // X lines the same with M_X; the Y digit with M_2 at k = k0 + 4 k1; conj(A)
-      const C* __restrict__ m2 = lsm;
-      const C* __restrict__ mx = lsm + 16;
-      const C* __restrict__ mz = lsm + 32;
+      const E* __restrict__ m2 = lsm;
+      const E* __restrict__ mx = lsm + 16;
+      const E* __restrict__ mz = lsm + 32;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], ltab[zg + 64u * k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], ltab[zg + 64u * k]);
       dft16<T, false>(x);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mz[k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], mz[k]);
       dft16<T, true>(x);
       z_to_lds(x);
       __syncthreads();
@@ -227,26 +229,26 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       __syncthreads();
       dft16<T, false>(x);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], mx[k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], mx[k]);
       dft16<T, true>(x);
       x_to_lds(x);
       __syncthreads();
       lds_to_y(x);
       __syncthreads();
-      C m[4];
+      E m[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) m[j] = m2[oth + 4 * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         dft4(&x[4 * i], false);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmul(x[4 * i + j], m[j]);
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], m[j]);
         dft4(&x[4 * i], true);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = cmulc(x[4 * i + j], ltab[yg + 16u * j + 64u * i]);
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], ltab[yg + 16u * j + 64u * i], true);
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -254,7 +256,7 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
     } else {
       // forward half: A factors, DFT along Z, X, then the 4-point Y digit
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], ltab[zg + 64u * k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], ltab[zg + 64u * k]);
       dft16<T, false>(x);
       z_to_lds(x);
       __syncthreads();
@@ -269,13 +271,13 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       for (int i = 0; i < 4; ++i) dft4(&x[4 * i], false);
       if constexpr (KIND == SPL_B_FWD) {
         // k0 = j: twiddle W16^(n0 k0) and the low digit's A factor c(n0)
-        C s[4];
+        E s[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) s[j] = lsm[4 * oth + j];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) x[4 * i + j] = cmul(x[4 * i + j], s[j]);
+          for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], s[j]);
       }
       if constexpr (KIND == SPL_C_MOM) {
         // momentum moments: every axis is transformed; axis axY has k = k0 + 4 k1

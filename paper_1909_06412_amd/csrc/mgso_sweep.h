@@ -8,13 +8,13 @@ namespace mgk {
 // Direction / table use of a sweep.
 enum : int { DIR_FWD = 0, DIR_INV = 1 };
 
-// Per-axis tables of a packet in the storage precision:
+// Per-axis tables of a packet, table entries of the storage precision (make_te):
 //   Atab[l][j] = (-1)^j exp(-i p_ctr,l j dq_l / hbar) / sqrt(N_l)   (forward pre, inverse post conj)
 //   Mtab[l][k] = exp(-i [h p_l^2 / (2 m_l) - delta_l p_l] / hbar)  (inverse pre)
 template <typename T> struct Tables {
-  const typename CT<T>::type* tw;   // twiddles (shared, offsets per axis length)
-  const typename CT<T>::type* A;
-  const typename CT<T>::type* M;
+  const typename TE<T>::type* tw;   // twiddles (shared, offsets per axis length)
+  const typename TE<T>::type* A;
+  const typename TE<T>::type* M;
 };
 
 // Load one tile of sweep `sw` into LDS (zero padding outside a ragged tile).
@@ -121,7 +121,7 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
   int cur = 0;
   for (int ai = 0; ai < sw.b - sw.a; ++ai) {
     const AxisDesc& ax = G.ax[sw.a + ai];
-    const C* tw = tb.tw + ax.tw_off;
+    const typename TE<T>::type* tw = tb.tw + ax.tw_off;
     if constexpr (PP) {
       if (!inv)
         tile_axis_fft_pp<T, NTHR>(lds, lds + TM, &cur, Tn, ax, sw.S[ai], sw.dS[ai], false, tw, tb.A + ax.tab_off,
@@ -210,8 +210,7 @@ __device__ __forceinline__ void fin_potential(const PacketGeom& G, PacketState& 
 // (sgn = -1 builds conj(M), used by the adjoint of the kinetic substep)
 template <typename T, int NT>
 __device__ __forceinline__ void build_M_tables(const PacketGeom& G, const PacketState& st, double h,
-                                               typename CT<T>::type* M, double sgn = 1.0) {
-  typedef typename CT<T>::type C;
+                                               typename TE<T>::type* M, double sgn = 1.0) {
   for (int l = 0; l < G.D; ++l) {
     const AxisDesc& ax = G.ax[l];
     for (int k = threadIdx.x; k < ax.n; k += NT) {
@@ -219,15 +218,14 @@ __device__ __forceinline__ void build_M_tables(const PacketGeom& G, const Packet
       const double phi = sgn * (h * 0.5 * ax.minv * p * p - st.delta[l] * p) / G.hbar;
       double s, c;
       sincos(phi, &s, &c);
-      M[ax.tab_off + k] = C{(decltype(C().x))c, (decltype(C().x))(-s)};
+      M[ax.tab_off + k] = make_te<T>(c, -s);
     }
   }
 }
 
 // A_l(j) = (-1)^j exp(-i p_ctr,l j dq_l / hbar) / sqrt(N_l)
 template <typename T, int NT>
-__device__ __forceinline__ void build_A_tables(const PacketGeom& G, const PacketState& st, typename CT<T>::type* A) {
-  typedef typename CT<T>::type C;
+__device__ __forceinline__ void build_A_tables(const PacketGeom& G, const PacketState& st, typename TE<T>::type* A) {
   for (int l = 0; l < G.D; ++l) {
     const AxisDesc& ax = G.ax[l];
     const double inv_sqrt = 1.0 / sqrt((double)ax.n);
@@ -236,7 +234,7 @@ __device__ __forceinline__ void build_A_tables(const PacketGeom& G, const Packet
       double s, c;
       sincos(phi, &s, &c);
       const double sg = (j & 1) ? -inv_sqrt : inv_sqrt;
-      A[ax.tab_off + j] = C{(decltype(C().x))(sg * c), (decltype(C().x))(-sg * s)};
+      A[ax.tab_off + j] = make_te<T>(sg * c, -sg * s);
     }
   }
 }

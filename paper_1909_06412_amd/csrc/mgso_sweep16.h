@@ -43,18 +43,20 @@ template <typename T> struct S16Args {
   const PotDesc* pot;
   const typename CT<T>::type* src;
   typename CT<T>::type* dst;
-  const typename CT<T>::type* AG;
-  const typename CT<T>::type* MG;
+  const typename TE<T>::type* AG;
+  const typename TE<T>::type* MG;
   double* partials;
   S16Desc d;
   double h;
 };
 
 // 16-point DFT in registers, natural order in and out (4 x 4 decomposition).
+// The twiddles are applied with compensated constants in complex64 (kmul, crotk):
+// each acts as the exact root of unity, so the DFT keeps the norm on average.
 template <typename T, bool INV, typename C> __device__ __forceinline__ void dft16(C* x) {
-  const T c1 = (T)0.92387953251128675612818318939679;  // cos(pi/8)
-  const T s1 = (T)0.38268343236508977172845998403040;  // sin(pi/8)
-  const T r2 = (T)0.70710678118654752440084436210485;
+  const double c1 = 0.92387953251128675612818318939679;  // cos(pi/8)
+  const double s1 = 0.38268343236508977172845998403040;  // sin(pi/8)
+  const double r2 = 0.70710678118654752440084436210485;
   C y[16];
   // DFT4 over n1 for each n2: inputs x[4 n1 + n2]
 #pragma unroll
@@ -67,16 +69,20 @@ template <typename T, bool INV, typename C> __device__ __forceinline__ void dft1
   // twiddles W16^(n2 k1), W16 = exp(-+ 2 pi i / 16)
   auto tw = [&](C v, int m) -> C {
     // exp(-i pi m / 8) for forward, conjugate for inverse
-    T c, s;
+    const double sg = INV ? 1.0 : -1.0;
     switch (m) {
-      case 1: c = c1; s = s1; break;
-      case 2: c = r2; s = r2; break;
-      case 3: c = s1; s = c1; break;
-      case 6: c = -r2; s = r2; break;
-      default: c = -c1; s = -s1; break;  // m = 9: cos(9pi/8) = -c1, sin(9pi/8) = -s1
+      case 1: return crotk<T>(v, c1, sg * s1);
+      case 3: return crotk<T>(v, s1, sg * c1);
+      case 9: return crotk<T>(v, -c1, -sg * s1);  // cos(9pi/8) = -c1, sin(9pi/8) = -s1
+      case 2: {  // r2 (1 -+ i)
+        const T a = INV ? v.x - v.y : v.x + v.y, b = INV ? v.x + v.y : v.y - v.x;
+        return C{kmul<T>(a, r2), kmul<T>(b, r2)};
+      }
+      default: {  // m = 6: r2 (-1 -+ i)
+        const T a = INV ? -v.x - v.y : v.y - v.x, b = INV ? v.x - v.y : -v.x - v.y;
+        return C{kmul<T>(a, r2), kmul<T>(b, r2)};
+      }
     }
-    if (!INV) s = -s;
-    return C{v.x * c - v.y * s, v.x * s + v.y * c};
   };
   y[4 * 1 + 1] = tw(y[5], 1);
   y[4 * 1 + 2] = tw(y[6], 2);
@@ -106,9 +112,11 @@ __device__ __forceinline__ uint32_t pad16(uint32_t t) { return t + (t >> 4); }
 // carry.)
 static inline bool pot_is_cubic(int kind) { return kind != 2; }
 
-template <typename T> __device__ __forceinline__ typename CT<T>::type phase_t(double phi);
-template <> __device__ __forceinline__ float2 phase_t<float>(double phi) { return phase_poly(phi); }
-template <> __device__ __forceinline__ double2 phase_t<double>(double phi) { return phase_poly64(phi); }
+// v exp(-i phi): complex64 by mul_phase_f32, complex128 by the FP64 series.
+template <typename T, typename C> __device__ __forceinline__ C mul_phase16(C v, double phi) {
+  if constexpr (sizeof(T) == 4) return mul_phase_f32(v, phi);
+  else return cmul(v, phase_poly64(phi));
+}
 
 // Potential part of the line epilogue (Sec. II.G.1, Eqs. (45), (47)) for a line
 // along packet axis L whose other indices are jfix.  With u = x - x_c (x_c the
@@ -277,7 +285,7 @@ __device__ __forceinline__ void line_epilogue(typename CT<T>::type* x, int L, ui
     for (int k = 0; k < 16; ++k) {
       const double sk = (double)(k - 8);
       const double phi = cp[0] + sk * cp[1] + (sk * sk) * cp[2] + (sk * sk * sk) * cp[3];
-      x[k] = cmul(x[k], phase_t<T>(phi));
+      x[k] = mul_phase16<T>(x[k], phi);
     }
   }
 }
@@ -292,11 +300,12 @@ __host__ __device__ constexpr int k16_threads(int K) { return K < 3 ? 512 : 256;
 __host__ __device__ constexpr uint32_t k16_tile_lds(int K) {
   return K > 1 ? (uint32_t)(16 * k16_threads(K)) + (uint32_t)k16_threads(K) : 0u;
 }
-__host__ __device__ constexpr uint32_t k16_lds_elems(int K, bool INV) {
-  return k16_tile_lds(K) + (K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u);
+__host__ __device__ constexpr uint32_t k16_lds_tab(int K, bool INV) {
+  return K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u;
 }
 template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, bool INV) {
-  const size_t b = (size_t)k16_lds_elems(K, INV) * 2 * sizeof(T);
+  // the tile in complex elements, then the tables in 16-byte table entries
+  const size_t b = (size_t)k16_tile_lds(K) * 2 * sizeof(T) + (size_t)k16_lds_tab(K, INV) * 16;
   const size_t red = (size_t)(k16_threads(K) / 64) * MGK_NACC * sizeof(double);
   return b > red ? b : red;
 }
@@ -335,15 +344,16 @@ void k_sweep16(S16Args<T> a) {
   const uint64_t off = G.off;  // read once: stores to dst must not force reloads
   const C* __restrict__ src = a.src + off;
   C* __restrict__ dst = a.dst + off;
-  const C* __restrict__ AG = a.AG + d.gtab_off;
-  const C* __restrict__ MG = a.MG + d.gtab_off;
+  typedef typename TE<T>::type E;
+  const E* __restrict__ AG = a.AG + d.gtab_off;
+  const E* __restrict__ MG = a.MG + d.gtab_off;
   __shared__ LineCst lc;
   __shared__ double tcs[2 * MGK_MAXD + 1];  // per-tile outer-axis terms (Henon-Heiles, contiguous tiles)
   if (EPI == EPI_V) stage_line_cst(lc, G, *a.st, *a.pot);
   // Strided tiles keep the sweep's group tables (16^K entries) in LDS for the
   // whole launch; the table index of a thread's points is the same in every tile.
-  C* __restrict__ ltab = lds + k16_tile_lds(K);
-  C* __restrict__ lsto = ltab + (1u << (4 * K));
+  E* __restrict__ ltab = reinterpret_cast<E*>(lds + k16_tile_lds(K));
+  E* __restrict__ lsto = ltab + (1u << (4 * K));
   if constexpr (KIND == 1) {
     for (uint32_t i = t; i < (1u << (4 * K)); i += NT) {
       ltab[i] = INV ? MG[i] : AG[i];
@@ -395,7 +405,7 @@ void k_sweep16(S16Args<T> a) {
     auto tab_stride = [&](uint32_t S_) -> uint32_t { return KIND == 0 ? S_ : (S_ >> d.lr); };
 
     C x[16];
-    C pv[KIND == 1 ? 16 : 1];  // strided inverse: the conj(A) factors of the store
+    E pv[KIND == 1 ? 16 : 1];  // strided inverse: the conj(A) factors of the store
     // ---- first axis: the outermost group axis (largest tile stride), coalesced
     int e = 0;
     uint32_t S = 1u << d.lS[0];
@@ -403,7 +413,7 @@ void k_sweep16(S16Args<T> a) {
     {
       // uniform (scalar) base per point k + a 32-bit per-lane offset: the loads
       // use scalar-base addressing and stay in flight together
-      const C* __restrict__ pre = KIND == 1 ? ltab : (INV ? MG : AG);
+      const E* __restrict__ pre = KIND == 1 ? ltab : (INV ? MG : AG);
       const uint32_t ts = tab_stride(S);
       const uint32_t glane = g_of(tau0);
       if (!PIPE) load_first(tile);
@@ -416,12 +426,12 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           pv[k] = lsto[k * ts + glane];
-          x[k] = cmul(x[k], pv[k]);
+          x[k] = tmul<T>(x[k], pv[k]);
         }
         dft16<T, false>(x);
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = cmul(x[k], pre[k * ts + glane]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], pre[k * ts + glane]);
       dft16<T, INV>(x);
     }
     // ---- inner axes through LDS
@@ -461,7 +471,7 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         C v = x[k];
-        if (INV) v = cmulc(v, pv[k]);
+        if (INV) v = tmul<T>(v, pv[k], true);
         C* __restrict__ bk = tdst + (uint64_t)k * ms;
         bk[lane] = v;
       }
@@ -557,13 +567,13 @@ void k_sweep16(S16Args<T> a) {
         C v = lds[pad16(t + 256 * m)];
         if (EPI == EPI_V) {
           if constexpr (sizeof(T) == 4) {
-            v = cmul(v, phase_t<T>(ph));
+            v = mul_phase16<T>(v, ph);
             ph += d1;
             d1 += d2;
             d2 += d3;
           } else {
             const double sm = (double)(m - 8);
-            v = cmul(v, phase_t<T>(cp[0] + sm * cp[1] + (sm * sm) * cp[2] + (sm * sm * sm) * cp[3]));
+            v = mul_phase16<T>(v, cp[0] + sm * cp[1] + (sm * sm) * cp[2] + (sm * sm * sm) * cp[3]);
           }
           if (INV) {
             // |AG| = (1/sqrt(16))^K = 4^-K (exact power of two); (-1)^m from the line axis
@@ -573,7 +583,7 @@ void k_sweep16(S16Args<T> a) {
             v.y *= sg;
           }
         } else if (INV) {
-          v = cmulc(v, AG[t + 256 * m]);
+          v = tmul<T>(v, AG[t + 256 * m], true);
         }
         tdst[256 * m + t] = v;
       }

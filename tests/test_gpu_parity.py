@@ -42,17 +42,24 @@ def rel_err(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+def max_err(a, b):
+    """Element-wise error: max |a - b| over the grid relative to max |b|."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 def compare(w, nsteps, precision, tol, tol_ctr=None):
     wp, _ = oracle_run(w, nsteps)
     m = gpu_run(w, nsteps, precision)
     psi, q, p, t = m.get_state()
     tol_ctr = tol if tol_ctr is None else tol_ctr
     e = rel_err(psi, wp.physical())
-    print(f"[parity] {w['name']} {precision} steps={nsteps} state={e:.3e} "
+    em = max_err(psi, wp.physical())
+    print(f"[parity] {w['name']} {precision} steps={nsteps} state={e:.3e} max={em:.3e} "
           f"dq={np.max(np.abs(q - wp.q_ctr)):.3e} dp={np.max(np.abs(p - wp.p_ctr)):.3e}", flush=True)
     assert np.max(np.abs(q - wp.q_ctr)) < tol_ctr
     assert np.max(np.abs(p - wp.p_ctr)) < tol_ctr
     assert e < tol
+    assert em < tol
     m.close()
     return e
 
