@@ -290,6 +290,35 @@ mg_status mg_batch_autotune(mg_batch* b, double dt, int64_t probe_steps, double*
 /* Total points (sum over packets). */
 int64_t mg_batch_points(const mg_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops or harnesses that forbid hipMalloc): the propagation of mg_step
+ * (moving grid, Sec. II.G) as one call that allocates nothing on the device.
+ *
+ * psi_dev: the caller's device buffer of prod(N) complex values in `prec`
+ *   (interleaved float2 / double2, C-ordered), holding c_J = psi(q^J) sqrt(prod dq)
+ *   -- the layout of mg_state_ptr's buffer; 256-byte aligned; read and overwritten
+ *   in place with the state after nsteps steps of dt.
+ * q_ctr, p_ctr: host arrays [D], the grid centres on entry, overwritten with the
+ *   centres at the end.  Grid, masses, potential (as mg_set_potential) and scheme
+ *   (as mg_set_scheme) are those of the other entry points.
+ * The plan's small device buffers (plan, grid state, potential, twiddles, phase
+ * tables, per-workgroup partial sums) live in one file-scope device array of
+ * MG_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends; every valid grid
+ * fits (a larger plan returns MG_EINVAL).  Calls on one GPU share that array: calls
+ * that overlap on one GPU (other threads, other streams) race and must not be made.
+ * No device or pinned memory, stream, event or graph is created; the host side uses
+ * the C++ heap for the plan's bookkeeping.  Synchronises the stream.  Errors as
+ * mg_step (MG_EUNSTABLE leaves psi_dev and the centres unspecified); the message is
+ * mg_last_error(NULL).  Results equal those of mg_create + mg_set_state + mg_step on
+ * the same input bit for bit. */
+#define MG_NOALLOC_SCRATCH_BYTES (1u << 20)
+mg_status mg_propagate_noalloc(int D, const int32_t* N, const double* dq, const double* inv_mass, double hbar,
+                               mg_precision prec, mg_pot kind, const double* params, int nparams,
+                               mg_split split, mg_comp comp, int order, const double* gammas, int nstages,
+                               void* psi_dev, double* q_ctr, double* p_ctr, double dt, int64_t nsteps,
+                               void* hip_stream);
+
 const char* mg_last_error(const void* ctx_or_batch);
 
 #ifdef __cplusplus

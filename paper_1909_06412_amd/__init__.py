@@ -211,6 +211,33 @@ def from_workload(w: dict, precision=None, use_torch=True) -> MovingGrid:
     return mg
 
 
+def propagate_noalloc(psi_dev_ptr, N, dq, inv_mass, hbar, precision, potential, scheme, q_ctr, p_ctr,
+                      dt, nsteps, stream=None):
+    """mg_propagate_noalloc: nsteps of dt on the caller's device buffer (address
+    psi_dev_ptr, holding psi(q^J) sqrt(prod dq) in `precision`) without any device
+    allocation.  potential = (kind, params dict); scheme = (split, comp, order,
+    gammas or None).  Returns the new (q_ctr, p_ctr)."""
+    D = len(N)
+    kind, par = potential
+    pr = potential_params(kind, par, D)
+    split, comp, order, gammas = scheme
+    g = None if gammas is None else L.f64(gammas)
+    Narr = np.ascontiguousarray(np.asarray(N, dtype=np.int32))
+    q = L.f64(q_ctr, D).copy()
+    p = L.f64(p_ctr, D).copy()
+    if stream is None:
+        stream, _ = _torch_stream_and_alloc()
+    st = L.lib().mg_propagate_noalloc(D, Narr.ctypes.data_as(L._ip), L.dptr(L.f64(dq, D)),
+                                      L.dptr(L.f64(inv_mass, D)), float(hbar), _PREC[precision], _POT[kind],
+                                      L.dptr(pr) if pr.size else None, int(pr.size), _SPLIT[split],
+                                      _COMP[comp], int(order), L.dptr(g), 0 if g is None else int(g.size),
+                                      L.C.c_void_p(int(psi_dev_ptr)), L.dptr(q), L.dptr(p), float(dt),
+                                      int(nsteps), stream)
+    if st != 0:
+        raise L.MgError(st, (L.lib().mg_last_error(None) or b"").decode())
+    return q, p
+
+
 class MovingGridBatch:
     """Many independent wavepackets with their own grids, propagated by one
     persistent kernel launch per mg_batch_step (wraps an mg_batch)."""

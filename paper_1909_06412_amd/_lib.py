@@ -71,6 +71,9 @@ _SIGS = {
     "mg_batch_set_config": (C.c_int, [_vp, C.c_int]),
     "mg_batch_autotune": (C.c_int, [_vp, C.c_double, C.c_int64, _dp, _ip]),
     "mg_batch_points": (C.c_int64, [_vp]),
+    "mg_propagate_noalloc": (C.c_int, [C.c_int, _ip, _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, C.c_int,
+                                       C.c_int, C.c_int, C.c_int, _dp, C.c_int, _vp, _dp, _dp, C.c_double,
+                                       C.c_int64, _vp]),
     "mg_last_error": (C.c_char_p, [_vp]),
 }
 

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1707,3 +1708,4 @@ const char* mg_last_error(const void* p) {
 // ===========================================================================
 #include "mgso_batch.inc"
 #include "mgso_adjoint.inc"
+#include "mgso_noalloc.inc"

@@ -94,3 +94,22 @@ def test_binding_knows_every_batch_launch_shape():
     n = int(re.search(r"#define MG_BATCH_CONFIGS (\d+)", txt).group(1))
     import paper_1909_06412_amd as mg
     assert mg.MovingGridBatch.N_CONFIGS == n
+
+
+def test_noalloc_entry_rejects_bad_arguments_before_device_work(lib):
+    """mg_propagate_noalloc validates its arguments on the host: a missing buffer, an
+    odd axis or a bad dt return MG_EINVAL with a message, before any HIP call."""
+    from paper_1909_06412_amd import _lib
+    N = np.asarray([8], dtype=np.int32)
+    one = np.ones(1)
+    q, p = np.zeros(1), np.zeros(1)
+    st = lib.mg_propagate_noalloc(1, N.ctypes.data_as(_lib._ip), _lib.dptr(one), _lib.dptr(one), 1.0, 0, 0,
+                                  None, 0, 0, 0, 2, None, 0, None, _lib.dptr(q), _lib.dptr(p), 0.1, 1, None)
+    assert st == _lib.MG_EINVAL
+    assert b"bad argument" in lib.mg_last_error(None)
+    st = lib.mg_propagate_noalloc(1, N.ctypes.data_as(_lib._ip), _lib.dptr(one), _lib.dptr(one), 1.0, 0, 0,
+                                  None, 0, 0, 0, 2, None, 0, ctypes.c_void_p(256), _lib.dptr(q), _lib.dptr(p),
+                                  float("nan"), 1, None)
+    assert st == _lib.MG_EINVAL
+    hdr = open(HEADER).read()
+    assert int(re.search(r"#define MG_NOALLOC_SCRATCH_BYTES \(1u << (\d+)\)", hdr).group(1)) == 20
