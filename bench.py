@@ -61,32 +61,31 @@ def cpu_sample(name):
     return W.harmonic_1d(), 1000, "1000 Strang steps of the 64-point oscillator"
 
 
-def run_cpu_baseline(name):
+def run_cpu_baseline(name, workers=1):
+    """The oracle as it stands, timed on a bounded sample of the workload.  workers:
+    threads of its FFT library primitive (the pointwise NumPy work stays on one)."""
     import oracle as O
-    w, nsteps, desc = cpu_sample(name)
-    if isinstance(w, list):
+    O.grid.set_fft_workers(workers)
+    try:
+        w, nsteps, desc = cpu_sample(name)
+        ws = w if isinstance(w, list) else [w]
         t0 = time.perf_counter()
         pts = 0
-        for wi in w:
+        for wi in ws:
             g = O.Grid(wi["N"], wi["dq"], wi["hbar"])
             wp = O.gaussian(g, wi["q0"], wi["p0"], wi["sigma"])
             pot = O.potentials.from_spec(*wi["potential"], wi["D"])
-            O.run(wp, wi["dt"], nsteps, O.composition(wi["comp"], wi["order"]), pot, wi["inv_mass"],
-                  wi["split"])
+            gam = O.composition(wi["comp"], wi["order"])
+            if len(ws) == 1:
+                t0 = time.perf_counter()       # a single grid: time the propagation only
+            O.run(wp, wi["dt"], nsteps, gam, pot, wi["inv_mass"], wi["split"])
             pts += int(np.prod(wi["N"]))
         dt = time.perf_counter() - t0
-        return {"value": pts * nsteps / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-                "sample": f"{desc}, FP64 NumPy, {dt:.1f} s"}
-    g = O.Grid(w["N"], w["dq"], w["hbar"])
-    wp = O.gaussian(g, w["q0"], w["p0"], w["sigma"])
-    pot = O.potentials.from_spec(*w["potential"], w["D"])
-    gam = O.composition(w["comp"], w["order"])
-    t0 = time.perf_counter()
-    O.run(wp, w["dt"], nsteps, gam, pot, w["inv_mass"], w["split"])
-    dt = time.perf_counter() - t0
-    pts = int(np.prod(w["N"]))
-    return {"value": pts * nsteps / dt, "unit": "grid-point-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{desc}, FP64 NumPy, {dt:.1f} s"}
+    finally:
+        O.grid.set_fft_workers(1)
+    return {"value": pts * nsteps / dt, "unit": "grid-point-steps/s", "cores": workers, "kind": "oracle",
+            "sample": f"{desc}, FP64 NumPy/SciPy (FFT on {workers} thread{'s' if workers > 1 else ''}), "
+                      f"{dt:.1f} s"}
 
 
 # Sources the single-grid sweep kernels and their launches are built from (the
@@ -209,7 +208,7 @@ def main_batch(args):
                    "launch": "autotuned shape: one persistent kernel per call, or one launch per sweep",
                    "launch_shape": tuned},
     }
-    if not args.no_fp64:
+    if not args.no_c64:
         el2, _, obs2, _ = batch_run(W.morse_batch(precision="c128"), "c128", args.steps, args.warmup)
         d = max(abs(a["norm"] - b_["norm"]) for a, b_ in zip(obs, obs2))
         d = max(d, max(float(np.max(np.abs(a["q"] - b_["q"]))) for a, b_ in zip(obs, obs2)))
@@ -242,15 +241,120 @@ def calibrate_copy():
                       "best_ms": best * 1e3, "GB_s": 2 * n * 8 / best / 1e9}), flush=True)
 
 
+def roofline_of(w, precision, prof):
+    """Roofline entry of the kernel class with the largest total time: algorithmic
+    bytes per launch / its average launch time from HIP events over the timed steps."""
+    cls, launches, total_ms, bytes_per = prof
+    avg_ms = total_ms / max(launches, 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    label = kernel_label(w, precision, cls)
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(w, precision, label),
+            "kernel": label, "sweep": cls[0], "avg_ms": avg_ms, "launches": launches,
+            "bytes_per_launch": bytes_per}
+
+
+SAMPLE_POINTS = 1 << 16
+
+
+def sampled_state(m, idx):
+    """The device state at flat indices idx, as complex128 on the host."""
+    import torch
+    v = m.state_view()
+    return v.index_select(0, torch.from_numpy(idx).to(v.device)).to(torch.complex128).cpu().numpy()
+
+
+C2_SCHEMES = (("strang", 2), ("suzuki", 4), ("triple_jump", 4), ("triple_jump", 6), ("suzuki", 6),
+              ("triple_jump", 8), ("triple_jump", 10))
+
+
+def c2_gate(tol=1e-6, max_stages=20000):
+    """"c64 vs FP64 at <= 1e-6 error" on the 3-D harmonic model (32^3, seed 0, t_f = 5).
+    Every listed scheme (order 2-10, dt 0.1 ... 0.001, runs up to max_stages stages) in
+    both precisions, timed as whole mg_step calls; error = relative l2 distance at t_f
+    from a converged FP64 run on the same grid (10th-order triple jump, dt = 0.005),
+    interpolated onto each run's final grid with mg_regrid.  Reports per precision the
+    fastest run within tol (or, if none, the most accurate one)."""
+    import paper_1909_06412_amd as mg
+    import torch
+    t_f = 5.0
+    base = W.harmonic_3d(seed=0, order=10, dt=0.005, t_final=t_f)
+    ref = mg.from_workload(base, precision="c128")
+    ref.step(base["dt"], base["steps"])
+    runs = []
+    for prec in ("c128", "c64"):
+        for comp, order in C2_SCHEMES:
+            stages_per_step = {"strang": 1, "suzuki": 5 ** (order // 2 - 1),
+                               "triple_jump": 3 ** (order // 2 - 1)}[comp]
+            w = W.harmonic_3d(seed=0, order=order, dt=0.1, t_final=t_f, precision=prec)
+            w["comp"] = comp
+            m = mg.from_workload(w, precision=prec)
+            for dt in W.HARMONIC_3D_DTS:
+                n = int(round(t_f / dt))
+                if n * stages_per_step > max_stages:
+                    continue
+                m.set_gaussian(w["q0"], w["p0"], w["sigma"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m.step(dt, n)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t0
+                psi, q, _, _ = m.get_state()
+                ref.regrid(q)
+                r_psi = ref.get_state()[0]
+                err = float(np.linalg.norm(psi - r_psi) / np.linalg.norm(r_psi))
+                runs.append({"precision": prec, "comp": comp, "order": order, "dt": dt,
+                             "stages": n * stages_per_step, "ms": round(el * 1e3, 3), "err": err})
+            m.close()
+    ref.close()
+    out = {"workload": "harmonic_3d_32^3_seed0", "t_final": t_f, "tolerance": tol,
+           "reference": "FP64, 10th-order triple jump, dt 0.005", "error": "relative l2 at t_final"}
+    for prec in ("c128", "c64"):
+        ok = [r for r in runs if r["precision"] == prec and r["err"] <= tol]
+        best = min(ok, key=lambda r: r["ms"]) if ok else min(
+            (r for r in runs if r["precision"] == prec), key=lambda r: r["err"])
+        out[prec] = dict(best, within_tolerance=bool(ok))
+    if out["c128"]["within_tolerance"] and out["c64"]["within_tolerance"]:
+        out["c64_speedup_at_tolerance"] = out["c128"]["ms"] / out["c64"]["ms"]
+    out["runs"] = [[r["precision"], r["comp"], r["order"], r["dt"], r["stages"], r["ms"], float(f"{r['err']:.3e}")]
+                   for r in runs]
+    return out
+
+
+def c3_extra(steps=2000):
+    """The 256^2 atom-diatom model: whole-call throughput in both precisions."""
+    out = {"workload": "morse_repulsion_256x256", "steps": steps}
+    for prec in ("c64", "c128"):
+        w = W.morse_repulsion_2d(precision=prec)
+        m, el, _, obs = timed_run(w, prec, steps, 10, profile=False)
+        m.close()
+        out[prec] = {"value": int(np.prod(w["N"])) * steps / el, "ms_per_step": el / steps * 1e3,
+                     "norm_minus_1": obs["norm"] - 1.0}
+    return out
+
+
+def c5_extra(steps=200):
+    """The 256 uneven atom-diatom packets, autotuned launch shape, both precisions."""
+    out = {"workload": "morse_batch_256_packets", "steps": steps}
+    for prec in ("c64", "c128"):
+        ws = W.morse_batch(precision=prec)
+        el, pts, obs, tuned = batch_run(ws, prec, steps, 10)
+        out[prec] = {"value": pts * steps / el, "ms_per_step": el / steps * 1e3, "points": pts,
+                     "launch_shape": tuned["shape"],
+                     "norm_minus_1_max": max(abs(o["norm"] - 1.0) for o in obs)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     # default steps: the unmerged end of a call (one extra kinetic half-substep) is
-    # spread over 20 steps of the 16^8 grid (about 12 s) and 200 steps of the batch
+    # spread over 20 steps of the 16^8 grid and 200 steps of the batch
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4", "c5"])
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-c64", action="store_true", help="skip the complex64 leg")
+    ap.add_argument("--no-extras", action="store_true", help="skip the C2 gate and the C3 / C5 keys")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a plain 4 GiB device copy (counter calibration) and exit")
@@ -270,43 +374,52 @@ def main():
     if args.workload == "c5":
         return main_batch(args)
     w = workload(args.workload)
-    prec = w["precision"]
     pts = int(np.prod(w["N"]))
-    m, el, prof, obs = timed_run(w, prec, args.steps, args.warmup, profile=True)
+    idx = np.random.default_rng(7).integers(0, pts, size=min(SAMPLE_POINTS, pts))
+    # the paper's precision (FP64) is the headline; complex64 is reported beside it
+    m, el, prof, obs = timed_run(w, "c128", args.steps, args.warmup, profile=True)
+    s128 = sampled_state(m, idx)
     m.close()
     del m
     torch.cuda.empty_cache()
     value = pts * args.steps / el
-    cls, launches, total_ms, bytes_per = prof
-    avg_ms = total_ms / max(launches, 1)
-    achieved = bytes_per / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    label = kernel_label(w, prec, cls)
-    traffic = measured_traffic(w, prec, label)
     out = {
         "metric": METRIC, "value": value, "unit": "grid-point-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64" if prec == "c64" else "c128", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+        "data": "synthetic",
         "config": {"workload": w["name"], "grid": "x".join(map(str, w["N"])), "points": pts,
                    "potential": w["potential"][0], "composition": w["comp"], "order": w["order"],
-                   "split": w["split"], "dt": w["dt"], "precision": prec},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": label, "sweep": cls[0], "avg_ms": avg_ms,
-                     "launches": launches, "bytes_per_launch": bytes_per},
+                   "split": w["split"], "dt": w["dt"], "precision": "c128"},
+        "roofline": roofline_of(w, "c128", prof),
     }
-    if not args.no_fp64 and prec == "c64":
-        m2, el2, _, obs2 = timed_run(w, "c128", args.steps, args.warmup, profile=False)
+    if not args.no_c64:
+        m2, el2, prof2, obs2 = timed_run(w, "c64", args.steps, args.warmup, profile=True)
+        s64 = sampled_state(m2, idx)
         m2.close()
         del m2
         torch.cuda.empty_cache()
         d = max(abs(obs[k] - obs2[k]) for k in ("norm", "Ekin", "Epot"))
         d = max(d, float(np.max(np.abs(obs["q"] - obs2["q"]))), float(np.max(np.abs(obs["p"] - obs2["p"]))))
-        out["fp64"] = {"value": pts * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
-                       "c64_speedup": el2 / el, "c64_vs_fp64_observable_maxdiff": d}
+        out["c64"] = {"value": pts * args.steps / el2, "ms_per_step": el2 / args.steps * 1e3,
+                      "speedup_vs_fp64": el / el2, "roofline": roofline_of(w, "c64", prof2),
+                      "vs_fp64": {"sampled_points": int(idx.size),
+                                  "rel_l2": float(np.linalg.norm(s64 - s128) / np.linalg.norm(s128)),
+                                  "max_rel": float(np.max(np.abs(s64 - s128)) / np.max(np.abs(s128))),
+                                  "observable_maxdiff": d,
+                                  "norm_minus_1": obs2["norm"] - 1.0, "fp64_norm_minus_1": obs["norm"] - 1.0}}
+    if not args.no_extras and args.workload == "c4":
+        log("C2 accuracy gate ...")
+        out["c2_gate"] = c2_gate()
+        log("C3 ...")
+        out["c3"] = c3_extra()
+        log("C5 ...")
+        out["c5"] = c5_extra()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = run_cpu_baseline(args.workload)
+        ncpu = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        out["cpu_baseline_all_cores"] = run_cpu_baseline(args.workload, workers=min(ncpu, 16))
     print(json.dumps(out), flush=True)
 
 

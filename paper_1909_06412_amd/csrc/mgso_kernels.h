@@ -635,8 +635,8 @@ __device__ __forceinline__ double pot_dtheta(const PotDesc& P, int D, const doub
 // (n = rint(2 phi / pi), r = phi - n pi/2 with pi/2 split in two parts so that the
 // reduction error stays near 1e-16 for |phi| < 1e6), sin r and cm = cos r - 1 by
 // their Taylor series (sin to r^9, cos to r^10) in FP32 with explicit FMAs, then
-// x (1 + cm) - i x sin r with the 1 kept exact inside the FMAs, then the quarter
-// turns (-i)^n as exact swaps and sign flips.  Keeping cos r as 1 + cm makes the
+// x + x cm - i x sin r with the 1 kept exact, then the quarter turns (-i)^n as exact
+// swaps and sign flips.  Keeping cos r as 1 + cm makes the
 // factor unitary to ~r^2 1e-7: cos r rounded to FP32 near 1 would instead leave
 // |exp(-i r)|^2 - 1 = r^2 exactly for every |r| < 2.4e-4 (cos r rounds to 1), a
 // steady norm gain wherever the potential phase is small.  On |r| <= pi/4 the
@@ -663,9 +663,13 @@ __device__ __forceinline__ float2 mul_phase_f32(float2 v, double phi) {
   pc = __builtin_fmaf(pc, r2, 0x1.555558p-5f);  // 1/24, one FP32 step up
   pc = __builtin_fmaf(pc, r2, -0.5f);
   const float cm = r2 * pc;
-  // v exp(-i r) = (x (1 + cm) + y sn, y (1 + cm) - x sn)
-  const float a = __builtin_fmaf(v.y, sn, __builtin_fmaf(v.x, cm, v.x));
-  const float b = __builtin_fmaf(-v.x, sn, __builtin_fmaf(v.y, cm, v.y));
+  // v exp(-i r) = (x + (x cm + y sn), y + (y cm - x sn)): the two small terms are summed
+  // before they meet x, so the one rounding to x's precision sees the whole change.
+  // (Rounded first as x + x cm, the decrement x cm < 0 is lost whenever it is below half
+  // an FP32 step of x, and |result|^2 gains sn^2: on a packet whose phases are mostly
+  // below 1e-3, a norm gain of about 7e-9 per potential substep.)
+  const float a = v.x + __builtin_fmaf(v.x, cm, v.y * sn);
+  const float b = v.y + __builtin_fmaf(v.y, cm, -v.x * sn);
   // times (-i)^q: q = 1 maps (a, b) to (b, -a), q = 2 to (-a, -b), q = 3 to (-b, a)
   const int q = (int)n & 3;
   const bool odd = (q & 1) != 0;
