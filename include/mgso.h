@@ -319,6 +319,10 @@ mg_status mg_propagate_noalloc(int D, const int32_t* N, const double* dq, const 
                                void* psi_dev, double* q_ctr, double* p_ctr, double dt, int64_t nsteps,
                                void* hip_stream);
 
+/* sha256 (hex) of the sources and compile flags the library was built from; the
+ * Python binding compares it with the sources beside it and refuses a stale build. */
+const char* mg_build_hash(void);
+
 const char* mg_last_error(const void* ctx_or_batch);
 
 #ifdef __cplusplus

@@ -75,6 +75,7 @@ _SIGS = {
                                        C.c_int, C.c_int, C.c_int, _dp, C.c_int, _vp, _dp, _dp, C.c_double,
                                        C.c_int64, _vp]),
     "mg_last_error": (C.c_char_p, [_vp]),
+    "mg_build_hash": (C.c_char_p, []),
 }
 
 
@@ -101,6 +102,11 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
+        from .build import source_hash
+        built, want = (L.mg_build_hash() or b"").decode(), source_hash()
+        if built != want:
+            raise ImportError(f"{LIB_PATH} was built from other sources (embedded {built[:16]}, "
+                              f"sources {want[:16]}): rebuild with `python -m paper_1909_06412_amd.build`")
         _lib = L
     return _lib
 

@@ -20,6 +20,22 @@ FLAGS = [
 ]
 
 
+def source_hash() -> str:
+    """sha256 over the library's sources (csrc/, include/) and the compile flags; the
+    build embeds it (mg_build_hash) and the binding refuses a library whose embedded
+    hash differs, so a stale build is never tested or measured."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(" ".join(FLAGS).encode())
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".h", ".inc")):
+                h.update(f.encode())
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(fh.read())
+    return h.hexdigest()
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):
@@ -30,7 +46,8 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     src = os.path.join(CSRC, "mgso.hip")
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-o", tmp, src]
+    cmd = [hipcc(), *FLAGS, f"-DMGSO_SOURCE_SHA256=\"{source_hash()}\"", "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC, "-o", tmp, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

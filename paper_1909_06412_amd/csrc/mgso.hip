@@ -1693,6 +1693,11 @@ mg_status mg_profile_read(mg_ctx* c, int64_t* launches, double* total_ms, double
   return MG_OK;
 }
 
+#ifndef MGSO_SOURCE_SHA256
+#define MGSO_SOURCE_SHA256 "unknown"
+#endif
+const char* mg_build_hash(void) { return MGSO_SOURCE_SHA256; }
+
 const char* mg_last_error(const void* p) {
   if (!p) return g_create_err.empty() ? "null context" : g_create_err.c_str();
   const uint32_t magic = *(const uint32_t*)p;

@@ -113,3 +113,15 @@ def test_noalloc_entry_rejects_bad_arguments_before_device_work(lib):
     assert st == _lib.MG_EINVAL
     hdr = open(HEADER).read()
     assert int(re.search(r"#define MG_NOALLOC_SCRATCH_BYTES \(1u << (\d+)\)", hdr).group(1)) == 20
+
+
+def test_binding_refuses_a_library_built_from_other_sources(monkeypatch):
+    """The library embeds the sha256 of its sources and flags; lib() compares it with
+    the sources beside it, so a stale build cannot be tested or measured silently."""
+    from paper_1909_06412_amd import _lib, build
+    L = _lib.lib()
+    assert L.mg_build_hash().decode() == build.source_hash()
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(build, "source_hash", lambda: "0" * 64)
+    with pytest.raises(ImportError, match="other sources"):
+        _lib.lib()
