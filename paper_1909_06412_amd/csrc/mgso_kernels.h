@@ -696,13 +696,16 @@ __device__ __forceinline__ double2 phase_poly64(double phi) {
   const double pc = ((((((((1.0 / 20922789888000.0) * r2 - 1.0 / 87178291200.0) * r2 + 1.0 / 479001600.0) * r2 -
                    1.0 / 3628800.0) * r2 + 1.0 / 40320.0) * r2 - 1.0 / 720.0) * r2 + 1.0 / 24.0) * r2 - 0.5);
   const double cs = 1.0 + r2 * pc;
+  // exp(i phi) = exp(i q pi/2) (cs + i sn): odd q swaps the pair, q = 1, 2 negate
+  // the cosine, q = 2, 3 the sine (selects and sign flips on the high word: no
+  // branches, which would diverge across a wave)
   const int q = (int)n & 3;
-  double c, s;
-  if (q == 0) { c = cs; s = sn; }
-  else if (q == 1) { c = -sn; s = cs; }
-  else if (q == 2) { c = -cs; s = -sn; }
-  else { c = sn; s = -cs; }
-  return double2{c, -s};
+  const bool odd = (q & 1) != 0;
+  const double c0 = odd ? sn : cs, s0 = odd ? cs : sn;
+  const uint64_t sc = (uint64_t)((q + 1) & 2) << 62, ss = (uint64_t)(q & 2) << 62;
+  const double c = __longlong_as_double(__double_as_longlong(c0) ^ (long long)sc);
+  const double ms = __longlong_as_double(__double_as_longlong(s0) ^ (long long)(ss ^ 0x8000000000000000ull));
+  return double2{c, ms};
 }
 
 // x exp(-i phi) with phi in FP64: complex64 through mul_phase_f32, complex128 with
