@@ -321,6 +321,15 @@ def c2_gate(tol=1e-6, max_stages=20000):
     return out
 
 
+def c1_extra():
+    """The 64-point oscillator: its whole 1000-step Strang run, complex128."""
+    w = W.harmonic_1d()
+    m, el, _, obs = timed_run(w, "c128", w["steps"], 0, profile=False)
+    m.close()
+    return {"workload": w["name"], "steps": w["steps"], "value": 64 * w["steps"] / el,
+            "ms_per_step": el / w["steps"] * 1e3, "norm_minus_1": obs["norm"] - 1.0}
+
+
 def c3_extra(steps=2000):
     """The 256^2 atom-diatom model: whole-call throughput in both precisions."""
     out = {"workload": "morse_repulsion_256x256", "steps": steps}
@@ -409,6 +418,8 @@ def main():
                                   "observable_maxdiff": d,
                                   "norm_minus_1": obs2["norm"] - 1.0, "fp64_norm_minus_1": obs["norm"] - 1.0}}
     if not args.no_extras and args.workload == "c4":
+        log("C1 ...")
+        out["c1"] = c1_extra()
         log("C2 accuracy gate ...")
         out["c2_gate"] = c2_gate()
         log("C3 ...")
