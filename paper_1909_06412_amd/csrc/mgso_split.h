@@ -63,7 +63,7 @@ struct SplitDesc {
   int32_t pX, pY, pZ;  // flat bit positions of the in-tile fields X (4 bits), Y (2), Z (4)
   int32_t pYc;         // flat bit position of the split axis' other digit (tile constant)
   int32_t axX, axY, axZ;
-  int32_t nf;          // tile-index fields, low first: flat position and width
+  int32_t nf;          // tile-index fields (tile index bits low first): flat position and width
   int32_t flo[4], fw[4];
   uint32_t ntiles;
   int32_t tab;         // this pass's 1024-entry tables in AG / MG

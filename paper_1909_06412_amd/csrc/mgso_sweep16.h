@@ -212,45 +212,59 @@ __device__ __forceinline__ void line_model(int L, const int* jfix, double M0, do
 // the outer axes is the same for the whole tile and comes from LDS (tcs: per outer
 // axis m its share of V, its gradient component without the x-dependent pair
 // (L-1, L), and q_{L-1}); the line along axis L adds the terms of its own axes.
-// Same quantities as line_model: the weight moments' gradient sums into acc and the
-// cubic V(s), s = k - 8.
-__device__ __forceinline__ void line_model_hh_tile(int L, int D, int j1, int j2, double M0, double M1, double M2,
-                                                   const LineCst& lc, const double* tcs, double* acc, double* cp) {
+// Same quantities as line_model, in two parts: the line's terms (which give the
+// cubic V(s), s = k - 8, before the weights are known) and, once the weight moments
+// are summed, their gradient sums into acc.
+struct HHTile {
+  double V0, gL, gL1, gL2, b1L, b2L, qm, xc;
+};
+__device__ __forceinline__ HHTile hh_tile_terms(int L, int j1, int j2, const LineCst& lc, const double* tcs) {
   const double ka = lc.pot.p[0], la = lc.pot.p[1];
-  const double d = lc.dq[L];
-  const double xc = lc.qc[L];
+  HHTile h;
+  h.xc = lc.qc[L];
+  const double xc = h.xc;
   const double y = lc.qc[L + 1] + (double)(j1 - 8) * lc.dq[L + 1];
   const double z = lc.qc[L + 2] + (double)(j2 - 8) * lc.dq[L + 2];
   const bool hasm = L >= 1;
-  const double qm = hasm ? tcs[2 * MGK_MAXD] : 0.0;
+  h.qm = hasm ? tcs[2 * MGK_MAXD] : 0.0;
+  const double qm = h.qm;
   double tout = 0.0;
 #pragma unroll
   for (int m = 0; m < MGK_MAXD; ++m)
     if (m < L) tout += tcs[m];
+  h.V0 = tout + (hasm ? la * (qm * qm * xc - xc * xc * xc * (1.0 / 3.0)) : 0.0) +
+         0.5 * ka * (xc * xc + y * y + z * z) + la * (xc * xc * y - y * y * y * (1.0 / 3.0)) +
+         la * (y * y * z - z * z * z * (1.0 / 3.0));
+  h.gL = ka * xc + (hasm ? la * (qm * qm - xc * xc) : 0.0) + 2.0 * la * xc * y;
+  h.gL1 = ka * y + la * (xc * xc - y * y) + 2.0 * la * y * z;
+  h.gL2 = ka * z + la * (y * y - z * z);
+  h.b1L = ka + 2.0 * la * y - (hasm ? 2.0 * la * xc : 0.0);
+  h.b2L = hasm ? -la : 0.0;
+  return h;
+}
+__device__ __forceinline__ void hh_tile_cp(const HHTile& h, int L, const LineCst& lc, double* cp) {
+  const double d = lc.dq[L];
+  cp[0] = h.V0;
+  cp[1] = h.gL * d;
+  cp[2] = 0.5 * h.b1L * d * d;
+  cp[3] = h.b2L * (1.0 / 3.0) * d * d * d;
+}
+__device__ __forceinline__ void hh_tile_acc(const HHTile& h, int L, int D, double M0, double M1, double M2,
+                                            const LineCst& lc, const double* tcs, double* acc) {
+  const double la = lc.pot.p[1];
+  const double d = lc.dq[L];
   const double S1 = d * M1, S2 = d * d * M2;
-  const double V0 = tout + (hasm ? la * (qm * qm * xc - xc * xc * xc * (1.0 / 3.0)) : 0.0) +
-                    0.5 * ka * (xc * xc + y * y + z * z) + la * (xc * xc * y - y * y * y * (1.0 / 3.0)) +
-                    la * (y * y * z - z * z * z * (1.0 / 3.0));
-  const double gL = ka * xc + (hasm ? la * (qm * qm - xc * xc) : 0.0) + 2.0 * la * xc * y;
-  const double gL1 = ka * y + la * (xc * xc - y * y) + 2.0 * la * y * z;
-  const double gL2 = ka * z + la * (y * y - z * z);
-  const double b1L = ka + 2.0 * la * y - (hasm ? 2.0 * la * xc : 0.0);
-  const double b2L = hasm ? -la : 0.0;
 #pragma unroll
   for (int m = 0; m < MGK_MAXD; ++m) {
     if (m >= D) continue;
     double v;
     if (m < L - 1) v = tcs[MGK_MAXD + m] * M0;
-    else if (m == L - 1) v = (tcs[MGK_MAXD + m] + 2.0 * la * qm * xc) * M0 + 2.0 * la * qm * S1;
-    else if (m == L) v = gL * M0 + b1L * S1 + b2L * S2;
-    else if (m == L + 1) v = gL1 * M0 + 2.0 * la * xc * S1 + la * S2;
-    else v = gL2 * M0;
+    else if (m == L - 1) v = (tcs[MGK_MAXD + m] + 2.0 * la * h.qm * h.xc) * M0 + 2.0 * la * h.qm * S1;
+    else if (m == L) v = h.gL * M0 + h.b1L * S1 + h.b2L * S2;
+    else if (m == L + 1) v = h.gL1 * M0 + 2.0 * la * h.xc * S1 + la * S2;
+    else v = h.gL2 * M0;
     acc[1 + m] += v;
   }
-  cp[0] = V0;
-  cp[1] = gL * d;
-  cp[2] = 0.5 * b1L * d * d;
-  cp[3] = b2L * (1.0 / 3.0) * d * d * d;
 }
 
 // Epilogue on a line held in registers (strided tiles): moments (REDP) or the
@@ -303,9 +317,13 @@ __host__ __device__ constexpr uint32_t k16_tile_lds(int K) {
 __host__ __device__ constexpr uint32_t k16_lds_tab(int K, bool INV) {
   return K < 3 ? (1u << (4 * K)) * (INV ? 2u : 1u) : 0u;
 }
+// complex64 contiguous tiles alternate between two tile buffers (the transposes'
+// reads then need no barrier of their own): 68 KiB, two workgroups per CU
+template <typename T> __host__ __device__ constexpr bool k16_pingpong(int K) { return K == 3 && sizeof(T) == 4; }
 template <typename T> __host__ __device__ constexpr size_t k16_lds_bytes(int K, bool INV) {
-  // the tile in complex elements, then the tables in 16-byte table entries
-  const size_t b = (size_t)k16_tile_lds(K) * 2 * sizeof(T) + (size_t)k16_lds_tab(K, INV) * 16;
+  // the tile(s) in complex elements, then the tables in 16-byte table entries
+  const size_t b = (size_t)k16_tile_lds(K) * (k16_pingpong<T>(K) ? 2 : 1) * 2 * sizeof(T) +
+                   (size_t)k16_lds_tab(K, INV) * 16;
   const size_t red = (size_t)(k16_threads(K) / 64) * MGK_NACC * sizeof(double);
   return b > red ? b : red;
 }
@@ -321,9 +339,13 @@ enum : int { SW_FULL = 0, SW_MOMENTS = 1, SW_ROUNDTRIP = 2, SW_SPLIT = 3, SW_SPL
 // sweep that then does the forward DFT, the M factor and the inverse DFT of the axis
 // in registers.  Same arithmetic as the two full sweeps, one HBM write and one read
 // fewer.
-template <typename T, int K, bool INV, int EPI, int PK = -1, int MODE = 0>
+// DT > 0 fixes the packet dimension at compile time (contiguous tiles only, where the
+// tile's first axis is a = DT - 3), so that the per-axis loops of the epilogue unroll
+// without tests on D.
+template <typename T, int K, bool INV, int EPI, int PK = -1, int MODE = 0, int DT = 0>
 __global__ __launch_bounds__(k16_threads(K)) __attribute__((amdgpu_waves_per_eu(2)))
 void k_sweep16(S16Args<T> a) {
+  static_assert(DT == 0 || (K == 3 && DT >= 3 && DT <= MGK_MAXD), "a fixed dimension needs a contiguous tile");
   static_assert(MODE == SW_FULL || (K == 1 && (MODE == SW_MOMENTS) == (!INV && EPI == EPI_REDP) &&
                                     (MODE == SW_ROUNDTRIP) == (INV && EPI == 0)),
                 "moments-only and round-trip sweeps are one-axis strided sweeps");
@@ -331,11 +353,18 @@ void k_sweep16(S16Args<T> a) {
   typedef typename CT<T>::type C;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   C* lds = reinterpret_cast<C*>(lds_raw);
+  // Ping-pong (complex64 contiguous tiles): the three transposes of a tile use
+  // buffers b0, b1, b0 and the next tile starts on b1.  Every write to a buffer then
+  // follows a barrier that comes after all reads of that buffer, so only the
+  // barrier after each write is needed (three per tile instead of six).
+  constexpr bool PP = k16_pingpong<T>(K);
+  C* lb0 = lds;
+  C* lb1 = lds + (PP ? k16_tile_lds(K) : 0u);
   const PacketGeom& G = *a.geom;
   const S16Desc d = a.d;
   // every 16^D plan has contiguous 16^3 tiles for K = 3 and strided tiles below
   constexpr int KIND = K == 3 ? 0 : 1;
-  const int D = G.D;
+  const int D = DT ? DT : G.D;
   const uint32_t t = threadIdx.x;
   double acc[MGK_NACC];
 #pragma unroll
@@ -366,6 +395,15 @@ void k_sweep16(S16Args<T> a) {
   // as the current tile's data has arrived; contiguous tiles: once the tile sits
   // in LDS, so that they overlap the epilogue and the stores).  Each tile is read
   // and written by one workgroup only, so this is safe in place.
+  // log2 of the tile stride of group axis e; a contiguous 16^3 tile has the strides
+  // 256, 16, 1 as constants, so that its LDS addresses below are one per-thread base
+  // plus immediate offsets
+  auto lS_of = [&](int e_) -> int { return KIND == 0 ? 4 * (K - 1 - e_) : d.lS[e_]; };
+  // LDS slot of point k of a line at tile position tau with stride S: pad16(tau + k S),
+  // which is pad16(tau) + k (S + S/16) when S is a multiple of 16 or tau is (S = 1)
+  auto lslot = [&](uint32_t tau, uint32_t S_, int k) -> uint32_t {
+    return KIND == 0 ? pad16(tau) + (uint32_t)k * (S_ + (S_ >> 4)) : pad16(tau + (uint32_t)k * S_);
+  };
   auto tile_flat0 = [&](uint32_t tl) -> uint64_t {
     if (KIND == 0) return (uint64_t)tl << 12;
     const uint32_t o = tl >> d.ltiles_i;
@@ -376,8 +414,8 @@ void k_sweep16(S16Args<T> a) {
   constexpr bool PIPE = sizeof(T) == 4;
   C xn[16];
   auto load_first = [&](uint32_t tl) {
-    const uint32_t S0 = 1u << d.lS[0];
-    const uint32_t tau = ((t >> d.lS[0]) << (d.lS[0] + 4)) + (t & (S0 - 1));
+    const uint32_t S0 = 1u << lS_of(0);
+    const uint32_t tau = ((t >> lS_of(0)) << (lS_of(0) + 4)) + (t & (S0 - 1));
     const uint64_t ms0 = KIND == 0 ? (uint64_t)S0 : ((uint64_t)(S0 >> d.lr) << d.lI);
     const uint32_t lane0 =
         KIND == 0 ? tau : (uint32_t)(((uint64_t)(tau >> d.lr) << d.lI) + (tau & ((1u << d.lr) - 1)));
@@ -389,6 +427,14 @@ void k_sweep16(S16Args<T> a) {
     }
   };
   if (PIPE && blockIdx.x < d.ntiles) load_first(blockIdx.x);
+  // A contiguous tile's first-axis factors (point k of thread t: entry t + 256 k of the
+  // group table) are the same in every tile: each thread keeps its sixteen in registers
+  E preg[KIND == 0 ? 16 : 1];
+  if constexpr (KIND == 0) {
+    const E* __restrict__ pre0 = INV ? MG : AG;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) preg[k] = pre0[256 * k + t];
+  }
 
   for (uint32_t tile = blockIdx.x; tile < d.ntiles; tile += gridDim.x) {
     const uint64_t flat0 = tile_flat0(tile);
@@ -408,8 +454,8 @@ void k_sweep16(S16Args<T> a) {
     E pv[KIND == 1 ? 16 : 1];  // strided inverse: the conj(A) factors of the store
     // ---- first axis: the outermost group axis (largest tile stride), coalesced
     int e = 0;
-    uint32_t S = 1u << d.lS[0];
-    uint32_t tau0 = ((t >> d.lS[0]) << (d.lS[0] + 4)) + (t & (S - 1));
+    uint32_t S = 1u << lS_of(0);
+    uint32_t tau0 = ((t >> lS_of(0)) << (lS_of(0) + 4)) + (t & (S - 1));
     {
       // uniform (scalar) base per point k + a 32-bit per-lane offset: the loads
       // use scalar-base addressing and stay in flight together
@@ -431,21 +477,22 @@ void k_sweep16(S16Args<T> a) {
         dft16<T, false>(x);
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], pre[k * ts + glane]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], KIND == 0 ? preg[k] : pre[k * ts + glane]);
       dft16<T, INV>(x);
     }
     // ---- inner axes through LDS
 #pragma unroll
     for (int ee = 1; ee < K; ++ee) {
+      C* const lb = (ee & 1) ? lb0 : lb1;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
+      for (int k = 0; k < 16; ++k) lb[lslot(tau0, S, k)] = x[k];
       __syncthreads();
       e = ee;
-      S = 1u << d.lS[e];
-      tau0 = ((t >> d.lS[e]) << (d.lS[e] + 4)) + (t & (S - 1));
+      S = 1u << lS_of(e);
+      tau0 = ((t >> lS_of(e)) << (lS_of(e) + 4)) + (t & (S - 1));
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = lds[pad16(tau0 + k * S)];
-      __syncthreads();
+      for (int k = 0; k < 16; ++k) x[k] = lb[lslot(tau0, S, k)];
+      if (!PP) __syncthreads();
       if (ee < K - 1) dft16<T, INV>(x);
     }
     // inverse: fetch the conj(A) factors of the store now, so that their latency
@@ -478,11 +525,11 @@ void k_sweep16(S16Args<T> a) {
     } else {
       // ---- contiguous tile: the last axis is contiguous.  Transpose through LDS;
       // thread t then owns positions t + 256 m, a line along the outermost group
-      // axis (packet axis a), and streams it: pass 1 reduces, pass 2 applies the
-      // phase and the conj(A) factor and stores 512 contiguous bytes per wave.
+      // axis (packet axis a), and streams it in one pass: reduces, applies the phase
+      // and the conj(A) factor and stores 512 contiguous bytes per wave.
       if constexpr (EPI == EPI_V && PK == 3) {
         // Henon-Heiles terms of the outer axes of this tile (one thread per axis)
-        const int L = d.a;
+        const int L = DT ? DT - 3 : d.a;
         if (t < (uint32_t)L) {
           const double ka = lc.pot.p[0], la = lc.pot.p[1];
           auto qo = [&](int l) {
@@ -503,52 +550,43 @@ void k_sweep16(S16Args<T> a) {
         }
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) lds[pad16(tau0 + k * S)] = x[k];
+      for (int k = 0; k < 16; ++k) lb0[lslot(tau0, S, k)] = x[k];
       __syncthreads();
       if (PIPE && KIND == 0 && tile + gridDim.x < d.ntiles) load_first(tile + gridDim.x);
-      double cp[4] = {0.0, 0.0, 0.0, 0.0};
+      // One pass over the line: per point the weight moments (REDP, V), the phase
+      // (V) or the store factor (plain inverse), and the store.  The potential's
+      // cubic along the line depends only on the line's position, so its phase is
+      // known before the weights; the moments' gradient sums go into acc after.
+      const int L = DT ? DT - 3 : d.a;
+      const int j1 = (int)((t >> 4) & 15u), j2 = (int)(t & 15u);  // fixed indices on axes L+1, L+2
+      int jfix[MGK_MAXD];
       if (EPI) {
-        const int L = d.a;
-        int jfix[MGK_MAXD];
         const uint64_t f = flat0 + t;
 #pragma unroll
         for (int l = 0; l < MGK_MAXD; ++l)
           if (l < D) jfix[l] = (int)((f >> (4 * (D - 1 - l))) & 15);
-        double wl = 0.0, ml = 0.0, m2 = 0.0;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-          const C y = lds[pad16(t + 256 * m)];
-          const double w = (double)y.x * (double)y.x + (double)y.y * (double)y.y;
-          wl += w;
-          ml += w * (double)(m - 8);
-          if (EPI == EPI_V) m2 += w * (double)((m - 8) * (m - 8));
+      }
+      double cp[4] = {0.0, 0.0, 0.0, 0.0};
+      HHTile hht{};
+      if (EPI == EPI_V) {
+        if constexpr (PK == 3) {
+          hht = hh_tile_terms(L, j1, j2, lc, tcs);
+          hh_tile_cp(hht, L, lc, cp);
+        } else {
+          double unused[MGK_NACC];
+          line_model<PK>(L, jfix, 0.0, 0.0, 0.0, D, lc, unused, cp);
         }
-        acc[0] += wl;
-        if (EPI == EPI_REDP) {
 #pragma unroll
-          for (int l = 0; l < MGK_MAXD; ++l)
-            if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
-        }
-        if (EPI == EPI_V) {
-          if constexpr (PK == 3)
-            line_model_hh_tile(L, D, (int)((t >> 4) & 15u), (int)(t & 15u), wl, ml, m2, lc, tcs, acc, cp);
-          else
-            line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, cp);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) cp[i] *= hh;
-          if (INV) {
-            // conj(AG) of the store folded into the same phase: along the line
-            // (axis L, index m = s + 8) its angle is ang_t + beta m, times (-1)^m
-            // (a contiguous tile holds the innermost three axes L, L+1, L+2; the
-            // thread's fixed indices there are (t >> 4) & 15 and t & 15)
-            const int j1 = (int)((t >> 4) & 15u), j2 = (int)(t & 15u);
-            const double ang_t = M_PI * (double)((j1 & 1) + (j2 & 1)) -
-                                 (lc.pc[L + 1] * lc.dq[L + 1] * (double)j1 +
-                                  lc.pc[L + 2] * lc.dq[L + 2] * (double)j2) * lc.ihb;
-            const double beta = -lc.pc[L] * lc.dq[L] * lc.ihb;
-            cp[0] += ang_t + 8.0 * beta;
-            cp[1] += beta;
-          }
+        for (int i = 0; i < 4; ++i) cp[i] *= hh;
+        if (INV) {
+          // conj(AG) of the store folded into the same phase: along the line
+          // (axis L, index m = s + 8) its angle is ang_t + beta m, times (-1)^m
+          const double ang_t = M_PI * (double)((j1 & 1) + (j2 & 1)) -
+                               (lc.pc[L + 1] * lc.dq[L + 1] * (double)j1 +
+                                lc.pc[L + 2] * lc.dq[L + 2] * (double)j2) * lc.ihb;
+          const double beta = -lc.pc[L] * lc.dq[L] * lc.ihb;
+          cp[0] += ang_t + 8.0 * beta;
+          cp[1] += beta;
         }
       }
       C* __restrict__ tdst = dst + flat0;
@@ -573,9 +611,16 @@ void k_sweep16(S16Args<T> a) {
         y = phase_poly64(d2);
         z = phase_poly64(d3);
       }
+      double wl = 0.0, ml = 0.0, m2 = 0.0;
 #pragma unroll
       for (int m = 0; m < 16; ++m) {
-        C v = lds[pad16(t + 256 * m)];
+        C v = lb0[pad16(t) + 272 * m];
+        if (EPI) {
+          const double wv = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          wl += wv;
+          ml += wv * (double)(m - 8);
+          if (EPI == EPI_V) m2 += wv * (double)((m - 8) * (m - 8));
+        }
         if (EPI == EPI_V) {
           if constexpr (sizeof(T) == 4) {
             // complex64: the phase argument itself by forward differences (three FP64
@@ -605,10 +650,33 @@ void k_sweep16(S16Args<T> a) {
         }
         tdst[256 * m + t] = v;
       }
-      __syncthreads();
+      if (EPI) {
+        acc[0] += wl;
+        if (EPI == EPI_REDP) {
+#pragma unroll
+          for (int l = 0; l < MGK_MAXD; ++l)
+            if (l < D) acc[1 + l] += (l == L) ? ml : wl * (double)(jfix[l] - 8);
+        }
+        if (EPI == EPI_V) {
+          if constexpr (PK == 3) {
+            hh_tile_acc(hht, L, D, wl, ml, m2, lc, tcs, acc);
+          } else {
+            double unused[4];
+            line_model<PK>(L, jfix, wl, ml, m2, D, lc, acc, unused);
+          }
+        }
+      }
+      if (PP) {
+        C* const sw = lb0;
+        lb0 = lb1;
+        lb1 = sw;
+      } else {
+        __syncthreads();
+      }
     }
   }
   if (EPI) {
+    if (PP) __syncthreads();  // the last tile's reads before the reduction reuses LDS
     // the inverse tables carry 1/sqrt(16) per axis: the sums above miss 16^-K
     if (INV) {
       const double sc = ldexp(1.0, -4 * K);
