@@ -75,11 +75,13 @@ class MovingGrid:
         self.h = h
         self._bufs = []
         if torch is not None:
+            # the state lives in a torch allocation; the out-of-place workspace (only
+            # observables and the naive grid mode use it, the step does not) is left
+            # to the library, which allocates it on first use
             nb = lib.mg_state_bytes(h)
             psi = torch.empty(nb, dtype=torch.uint8, device="cuda")
-            work = torch.empty(nb, dtype=torch.uint8, device="cuda")
-            self._bufs = [psi, work]
-            L.check(lib.mg_bind_buffers(h, psi.data_ptr(), work.data_ptr()), h)
+            self._bufs = [psi]
+            L.check(lib.mg_bind_buffers(h, psi.data_ptr(), None), h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -428,12 +428,22 @@ void k_sweep16(S16Args<T> a) {
   };
   if (PIPE && blockIdx.x < d.ntiles) load_first(blockIdx.x);
   // A contiguous tile's first-axis factors (point k of thread t: entry t + 256 k of the
-  // group table) are the same in every tile: each thread keeps its sixteen in registers
+  // group table) are the same in every tile: each thread keeps its sixteen in registers.
+  // The inverse potential sweep folds the store's conj(AG) into its epilogue: its sign
+  // (-1)^m into the phase, its magnitude 4^-K (a power of two, exact) into these factors.
+  constexpr bool FOLD = KIND == 0 && INV && EPI == EPI_V;
   E preg[KIND == 0 ? 16 : 1];
   if constexpr (KIND == 0) {
     const E* __restrict__ pre0 = INV ? MG : AG;
+    const T mag = FOLD ? (T)(1.0 / (double)(1 << (2 * K))) : (T)1;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) preg[k] = pre0[256 * k + t];
+    for (int k = 0; k < 16; ++k) {
+      preg[k] = pre0[256 * k + t];
+      if constexpr (FOLD) {
+        if constexpr (sizeof(T) == 4) preg[k] = E{preg[k].x * mag, preg[k].y * mag, preg[k].z * mag, preg[k].w * mag};
+        else preg[k] = E{preg[k].x * mag, preg[k].y * mag};
+      }
+    }
   }
 
   for (uint32_t tile = blockIdx.x; tile < d.ntiles; tile += gridDim.x) {
@@ -580,13 +590,14 @@ void k_sweep16(S16Args<T> a) {
         for (int i = 0; i < 4; ++i) cp[i] *= hh;
         if (INV) {
           // conj(AG) of the store folded into the same phase: along the line
-          // (axis L, index m = s + 8) its angle is ang_t + beta m, times (-1)^m
+          // (axis L, index m = s + 8) its angle is ang_t + beta m, times (-1)^m =
+          // exp(-i pi s) (its magnitude is in the first-axis factors)
           const double ang_t = M_PI * (double)((j1 & 1) + (j2 & 1)) -
                                (lc.pc[L + 1] * lc.dq[L + 1] * (double)j1 +
                                 lc.pc[L + 2] * lc.dq[L + 2] * (double)j2) * lc.ihb;
           const double beta = -lc.pc[L] * lc.dq[L] * lc.ihb;
           cp[0] += ang_t + 8.0 * beta;
-          cp[1] += beta;
+          cp[1] += beta + M_PI;
         }
       }
       C* __restrict__ tdst = dst + flat0;
@@ -638,13 +649,6 @@ void k_sweep16(S16Args<T> a) {
               y = cmul(y, z);
             }
           }
-          if (INV) {
-            // |AG| = (1/sqrt(16))^K = 4^-K (exact power of two); (-1)^m from the line axis
-            const T mag = (T)(1.0 / (double)(1 << (2 * K)));
-            const T sg = (m & 1) ? -mag : mag;
-            v.x *= sg;
-            v.y *= sg;
-          }
         } else if (INV) {
           v = tmul<T>(v, AG[t + 256 * m], true);
         }
@@ -678,7 +682,8 @@ void k_sweep16(S16Args<T> a) {
   if (EPI) {
     if (PP) __syncthreads();  // the last tile's reads before the reduction reuses LDS
     // the inverse tables carry 1/sqrt(16) per axis: the sums above miss 16^-K
-    if (INV) {
+    // (except where the first-axis factors carry it)
+    if (INV && !FOLD) {
       const double sc = ldexp(1.0, -4 * K);
 #pragma unroll
       for (int k = 0; k < MGK_NACC; ++k) acc[k] *= sc;
