@@ -55,6 +55,26 @@ template <typename C> __device__ __forceinline__ void gstore(C* p, uint64_t i, C
 #endif
 }
 
+// Streaming loads and stores of the state in the contiguous-tile sweeps: every point
+// is read once and written once per pass, so they carry the nontemporal hint
+// (measured on 16^8: those sweeps 3-5% faster; the split passes' 128-byte runs were
+// slower with it and keep plain accesses).
+template <typename C> struct NTVec;
+template <> struct NTVec<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct NTVec<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <typename C> __device__ __forceinline__ C ntload(const C* p) {
+  typedef typename NTVec<C>::type V;
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+  return C{v.x, v.y};
+}
+template <typename C> __device__ __forceinline__ void ntstore(C* p, C c) {
+  typedef typename NTVec<C>::type V;
+  V v;
+  v.x = c.x;
+  v.y = c.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return C{a.x + b.x, a.y + b.y}; }
 template <typename C> __device__ __forceinline__ C csub(C a, C b) { return C{a.x - b.x, a.y - b.y}; }
 template <typename C> __device__ __forceinline__ C cmul(C a, C b) {

@@ -423,7 +423,7 @@ void k_sweep16(S16Args<T> a) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const C* __restrict__ bk = ts0 + (uint64_t)k * ms0;
-      xn[k] = bk[lane0];
+      xn[k] = KIND == 0 ? ntload(bk + lane0) : bk[lane0];
     }
   };
   if (PIPE && blockIdx.x < d.ntiles) load_first(blockIdx.x);
@@ -652,7 +652,7 @@ void k_sweep16(S16Args<T> a) {
         } else if (INV) {
           v = tmul<T>(v, AG[t + 256 * m], true);
         }
-        tdst[256 * m + t] = v;
+        ntstore(tdst + 256 * m + t, v);
       }
       if (EPI) {
         acc[0] += wl;

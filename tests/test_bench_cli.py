@@ -22,9 +22,9 @@ def test_kernel_labels_of_profile_classes():
     import bench
     import workloads as W
     w = W.henon_heiles_8d()
-    assert bench.kernel_label(w, "c64", (0, 1, 4, 3, 0)) == "k_sweep16<float, 3, true, 4, 3, 0>"
-    assert bench.kernel_label(w, "c64", (0, 0, 0, 3, 0)) == "k_sweep16<float, 3, false, 0, -1, 0>"
-    assert bench.kernel_label(w, "c128", (3, 0, 1, 1, 1)) == "k_sweep16<double, 1, false, 1, -1, 1>"
+    assert bench.kernel_label(w, "c64", (0, 1, 4, 3, 0)) == "k_sweep16<float, 3, true, 4, 3, 0, 8>"
+    assert bench.kernel_label(w, "c64", (0, 0, 0, 3, 0)) == "k_sweep16<float, 3, false, 0, -1, 0, 0>"
+    assert bench.kernel_label(w, "c128", (3, 0, 1, 1, 1)) == "k_sweep16<double, 1, false, 1, -1, 1, 0>"
     # the three-pass plan: pass B forward / inverse, pass C moments-only / round trip
     assert bench.kernel_label(w, "c64", (1, 0, 0, 3, 3)) == "k_split<float, 0>"
     assert bench.kernel_label(w, "c64", (1, 1, 0, 3, 3)) == "k_split<float, 1>"
