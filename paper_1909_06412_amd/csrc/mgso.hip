@@ -29,6 +29,38 @@ using namespace mgk;
 // ===========================================================================
 // Kernels
 // ===========================================================================
+// Finalize modes.
+enum : int {
+  FIN_T = 1,        // <p> -> delta = h m^-1 <p>, q_ctr += delta, then the M tables
+  FIN_V = 2,        // <dV/dq> -> p_ctr -= h <dV/dq>, then the A tables
+  FIN_REGRID = 3,   // delta forced (h = 0), q_ctr += delta, then the M tables
+  FIN_OBSQ = 4,     // store position-grid sums
+  FIN_OBSP = 5,     // store momentum-grid sums
+  FIN_BUILD_A = 6,  // only rebuild the A tables from p_ctr
+  FIN_NORM = 7,     // scale = 1/sqrt(sum w) for a following renormalisation pass
+  FIN_NAIVE_A = 8,  // naive re-centring: p_ctr = <p>, delta = <q> - q_ctr (from the obs sums), A tables
+  FIN_NAIVE_M = 9   // naive re-centring: q_ctr += delta, M tables of the shift (h = 0)
+};
+
+template <typename T> struct FinArgs {
+  const PacketGeom* geom;
+  PacketState* st;
+  const double* partials;
+  int nblk;
+  int mode;
+  double h;
+  double forced[MGK_MAXD];
+  typename TE<T>::type* A;
+  typename TE<T>::type* M;
+  typename TE<T>::type* AG;   // group-combined tables (16-point path), may be null
+  typename TE<T>::type* MG;
+};
+
+// Body of the finalize (one workgroup of NTHR threads); also run at the end of a
+// one-workgroup sweep (k_sweep<T, true>), which saves a launch per substep on grids
+// that fit one tile.
+template <typename T> __device__ __forceinline__ void finalize_body(const FinArgs<T>& a);
+
 template <typename T> struct SweepArgs {
   const PacketGeom* geom;
   const PacketState* st;
@@ -39,10 +71,12 @@ template <typename T> struct SweepArgs {
   double* partials;  // [gridDim.x][MGK_NACC] when epi != 0
   int si, dir, epi;
   double h;
+  FinArgs<T> fin;    // FIN: the finalize this one-workgroup sweep ends with
 };
 
-// One sweep of one packet over all its tiles (grid-stride over tiles).
-template <typename T>
+// One sweep of one packet over all its tiles (grid-stride over tiles).  FIN: a
+// launch of one workgroup that then runs the finalize of its reduction itself.
+template <typename T, bool FIN = false>
 __global__ __launch_bounds__(NTHR) void k_sweep(SweepArgs<T> a) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   typedef typename CT<T>::type C;
@@ -56,6 +90,10 @@ __global__ __launch_bounds__(NTHR) void k_sweep(SweepArgs<T> a) {
     process_tile<T, NTHR, MGK_TMAX, false, 0, false, 8>(lds, G, a.si, tile, a.src, a.dst, a.tb, a.dir, a.epi, a.h,
                                                         *a.st, *a.pot, acc, true, true);
   if (a.epi) block_reduce<NTHR>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, (double*)lds_raw);
+  if constexpr (FIN) {
+    __syncthreads();  // the partial sums and every read of the tables before they are rebuilt
+    finalize_body<T>(a.fin);
+  }
 }
 
 // Pointwise pass over all points of a packet (standalone potential substep,
@@ -90,35 +128,12 @@ __global__ __launch_bounds__(NTHR) void k_pointwise(PointArgs<T> a) {
     block_reduce<NTHR>(acc, G.D + 2, a.partials + (size_t)blockIdx.x * MGK_NACC, red);
 }
 
-// Finalize modes.
-enum : int {
-  FIN_T = 1,        // <p> -> delta = h m^-1 <p>, q_ctr += delta, then the M tables
-  FIN_V = 2,        // <dV/dq> -> p_ctr -= h <dV/dq>, then the A tables
-  FIN_REGRID = 3,   // delta forced (h = 0), q_ctr += delta, then the M tables
-  FIN_OBSQ = 4,     // store position-grid sums
-  FIN_OBSP = 5,     // store momentum-grid sums
-  FIN_BUILD_A = 6,  // only rebuild the A tables from p_ctr
-  FIN_NORM = 7,     // scale = 1/sqrt(sum w) for a following renormalisation pass
-  FIN_NAIVE_A = 8,  // naive re-centring: p_ctr = <p>, delta = <q> - q_ctr (from the obs sums), A tables
-  FIN_NAIVE_M = 9   // naive re-centring: q_ctr += delta, M tables of the shift (h = 0)
-};
-
-template <typename T> struct FinArgs {
-  const PacketGeom* geom;
-  PacketState* st;
-  const double* partials;
-  int nblk;
-  int mode;
-  double h;
-  double forced[MGK_MAXD];
-  typename TE<T>::type* A;
-  typename TE<T>::type* M;
-  typename TE<T>::type* AG;   // group-combined tables (16-point path), may be null
-  typename TE<T>::type* MG;
-};
-
 template <typename T>
 __global__ __launch_bounds__(NTHR) void k_finalize(FinArgs<T> a) {
+  finalize_body<T>(a);
+}
+
+template <typename T> __device__ __forceinline__ void finalize_body(const FinArgs<T>& a) {
   typedef typename CT<T>::type C;
   const PacketGeom& G = *a.geom;
   PacketState& st = *a.st;
@@ -679,8 +694,7 @@ template <typename T> static Tables<T> tables_of(mg_ctx* c) {
   return Tables<T>{(const E*)c->d_tw, (const E*)c->d_A, (const E*)c->d_M};
 }
 
-template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, double h, int nblk, const double* forced) {
-  typedef typename CT<T>::type C;
+template <typename T> static FinArgs<T> fin_args(mg_ctx* c, int mode, double h, int nblk, const double* forced) {
   FinArgs<T> a;
   memset(&a, 0, sizeof(a));
   a.geom = c->d_geom;
@@ -696,6 +710,11 @@ template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, doub
   a.M = (E*)c->d_M;
   a.AG = (E*)c->d_AG;
   a.MG = (E*)c->d_MG;
+  return a;
+}
+
+template <typename T> static mg_status launch_finalize(mg_ctx* c, int mode, double h, int nblk, const double* forced) {
+  const FinArgs<T> a = fin_args<T>(c, mode, h, nblk, forced);
   hipLaunchKernelGGL(k_finalize<T>, dim3(1), dim3(NTHR), 0, c->stream, a);
   HIPCHK(c, hipGetLastError());
   return MG_OK;
@@ -759,9 +778,13 @@ static bool fast16_turn(const mg_ctx* c) {
 // Launch sweep si; returns the number of blocks (for the finalize).  fast = use
 // the 16-point kernel when the packet qualifies (only plain, REDP and V epilogues);
 // mode SW_MOMENTS / SW_ROUNDTRIP only where fast16_turn holds.
+// fin_mode != 0: the finalize that follows this sweep; a generic sweep of one
+// workgroup runs it itself (*fused = true) and the caller skips its launch.
 template <typename T>
 static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, const void* src, void* dst, int* nblk,
-                              bool fast = false, int mode = SW_FULL) {
+                              bool fast = false, int mode = SW_FULL, int fin_mode = 0, double fin_h = 0.0,
+                              bool* fused = nullptr) {
+  if (fused) *fused = false;
   typedef typename CT<T>::type C;
   if (mode != SW_FULL &&
       !(fast && fast16_turn(c) && si == c->geom.nsweeps - 1 &&
@@ -817,6 +840,9 @@ static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, con
   a.h = h;
   const int grid = grid_for(c->geom.sw[si].ntiles);
   *nblk = grid;
+  const bool fuse = fin_mode != 0 && grid == 1 && fused;
+  if (fuse) a.fin = fin_args<T>(c, fin_mode, fin_h, 1, nullptr);
+  else memset(&a.fin, 0, sizeof(a.fin));
   const size_t lds = (size_t)MGK_TMAX * sizeof(C);
   ProfEntry pe{};
   if (c->opt_profile) {
@@ -824,7 +850,12 @@ static mg_status launch_sweep(mg_ctx* c, int si, int dir, int epi, double h, con
     HIPCHK(c, hipEventCreate(&pe.e1));
     HIPCHK(c, hipEventRecord(pe.e0, c->stream));
   }
-  hipLaunchKernelGGL(k_sweep<T>, dim3(grid), dim3(NTHR), lds, c->stream, a);
+  if (fuse) {
+    hipLaunchKernelGGL((k_sweep<T, true>), dim3(grid), dim3(NTHR), lds, c->stream, a);
+    *fused = true;
+  } else {
+    hipLaunchKernelGGL((k_sweep<T, false>), dim3(grid), dim3(NTHR), lds, c->stream, a);
+  }
   HIPCHK(c, hipGetLastError());
   if (c->opt_profile) {
     HIPCHK(c, hipEventRecord(pe.e1, c->stream));
@@ -902,7 +933,9 @@ template <typename T> static mg_status launch_split(mg_ctx* c, int kind, void* b
 // next inverse_transform must turn too).
 template <typename T>
 static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int epi_last, int* nblk_last,
-                                   bool fast = false, bool turn = false) {
+                                   bool fast = false, bool turn = false, int fin_mode = 0, double fin_h = 0.0,
+                                   bool* fused = nullptr) {
+  if (fused) *fused = false;
   const int ns = c->geom.nsweeps;
   if (fast && turn && split_step(c)) {
     if (epi_last != EPI_REDP) return fail(c, MG_EINVAL, "internal: the three-pass plan reduces momentum moments");
@@ -916,7 +949,7 @@ static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int ep
     int nb;
     const int mode = turn && s == ns - 1 ? SW_MOMENTS : SW_FULL;
     mg_status r = launch_sweep<T>(c, s, DIR_FWD, s == ns - 1 ? epi_last : 0, 0.0, s == 0 ? src : dst, dst, &nb,
-                                  fast, mode);
+                                  fast, mode, s == ns - 1 ? fin_mode : 0, fin_h, s == ns - 1 ? fused : nullptr);
     if (r) return r;
     if (s == ns - 1) *nblk_last = nb;
   }
@@ -925,7 +958,8 @@ static mg_status forward_transform(mg_ctx* c, const void* src, void* dst, int ep
 
 template <typename T>
 static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, double hV, int* nblk_last,
-                                   bool fast = false, bool turn = false) {
+                                   bool fast = false, bool turn = false, int fin_mode = 0, bool* fused = nullptr) {
+  if (fused) *fused = false;
   const int ns = c->geom.nsweeps;
   if (fast && turn && split_step(c)) {
     int nb;
@@ -937,8 +971,8 @@ static mg_status inverse_transform(mg_ctx* c, void* buf, int epi_first_sweep, do
   for (int s = ns - 1; s >= 0; --s) {
     int nb;
     const int mode = turn && s == ns - 1 ? SW_ROUNDTRIP : SW_FULL;
-    mg_status r =
-        launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb, fast, mode);
+    mg_status r = launch_sweep<T>(c, s, DIR_INV, s == 0 ? epi_first_sweep : 0, hV, buf, buf, &nb, fast, mode,
+                                  s == 0 ? fin_mode : 0, hV, s == 0 ? fused : nullptr);
     if (r) return r;
     if (s == 0) *nblk_last = nb;
   }
@@ -950,10 +984,13 @@ template <typename T> static mg_status run_unit(mg_ctx* c, const Unit& u) {
   int nb = 0;
   if (u.hasT) {
     const bool turn = fast16_turn(c);
-    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb, true, turn))) return r;
-    if ((r = launch_finalize<T>(c, FIN_T, u.hT, nb, nullptr))) return r;
-    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb, true, turn))) return r;
-    if (u.hasV && (r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
+    bool fused = false;
+    if ((r = forward_transform<T>(c, c->psi, c->psi, EPI_REDP, &nb, true, turn, FIN_T, u.hT, &fused))) return r;
+    if (!fused && (r = launch_finalize<T>(c, FIN_T, u.hT, nb, nullptr))) return r;
+    if ((r = inverse_transform<T>(c, c->psi, u.hasV ? EPI_V : 0, u.hV, &nb, true, turn, u.hasV ? FIN_V : 0,
+                                  &fused)))
+      return r;
+    if (u.hasV && !fused && (r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
   } else if (u.hasV) {
     if ((r = launch_pointwise<T>(c, EPI_V, u.hV, &nb))) return r;
     if ((r = launch_finalize<T>(c, FIN_V, u.hV, nb, nullptr))) return r;
