@@ -32,11 +32,14 @@ def _same(a, b, tag):
     assert np.array_equal(qa, qb) and np.array_equal(pa_, pb_) and ta == tb
 
 
-@pytest.mark.parametrize("case", ["harmonic_32^3", "henon_heiles_16^4"])
+@pytest.mark.parametrize("case", ["harmonic_32^3", "henon_heiles_16^4", "harmonic_1d_64"])
 @pytest.mark.parametrize("precision", ["c64", "c128"])
 def test_step_graph_replays_match_eager(case, precision):
+    # harmonic_1d_64 fits one tile: its sweeps run the finalize in their one workgroup
     if case == "harmonic_32^3":
         w = W.harmonic_3d(seed=1, order=4, dt=0.05)
+    elif case == "harmonic_1d_64":
+        w = W.harmonic_1d()
     else:
         w = W.henon_heiles_8d(n=16, D=4, dq=0.625)
     a, b = _pair(w, precision)
