@@ -1017,7 +1017,12 @@ static mg_status collect_profile(mg_ctx* c) {
   return MG_OK;
 }
 
+// One-dimensional grids of at most 64 points: the whole call in one wave (mgso_small.inc).
+static bool small_path(const mg_ctx* c);
+template <typename T> static mg_status launch_small(mg_ctx* c, double dt, int64_t nsteps);
+
 template <typename T> static mg_status step_impl(mg_ctx* c, double dt, int64_t nsteps) {
+  if (small_path(c)) return launch_small<T>(c, dt, nsteps);
   mg_status r;
   if ((r = launch_finalize<T>(c, FIN_BUILD_A, 0.0, 0, nullptr))) return r;
   std::vector<Unit> units = lower_scheme(c->split, c->gam, dt, nsteps);
@@ -1765,4 +1770,5 @@ const char* mg_last_error(const void* p) {
 // ===========================================================================
 #include "mgso_batch.inc"
 #include "mgso_adjoint.inc"
+#include "mgso_small.inc"
 #include "mgso_noalloc.inc"
