@@ -1,8 +1,8 @@
 """mg_propagate_noalloc (the propagation of mg_step with its plan buffers in the
 library's file-scope device scratch array, no device allocation) against the
-context entry points on the same input: two calls in a row, the second on a
-smaller grid (and the other precision and sweep kernels), each equal to
-mg_create + mg_step bit for bit."""
+context entry points on the same input: calls in a row, each on a smaller grid
+(and the other precision and sweep kernels; the last one on the one-wave path of
+one-dimensional grids), each equal to mg_create + mg_step bit for bit."""
 import numpy as np
 import pytest
 
@@ -43,6 +43,8 @@ def test_noalloc_matches_step_two_calls():
     w2 = W.morse_repulsion_2d(64, 80, steps=0, precision="c128")
     w2["split"] = "VTV"
     _case(w2, "c128", 25)
+    # third call, smaller still: the 64-point oscillator (the one-wave path), complex64
+    _case(W.harmonic_1d(), "c64", 100)
 
 
 def test_noalloc_rejects_bad_arguments():
