@@ -149,6 +149,11 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
     for (int k = 0; k < 16; ++k) xn[k] = (src + zbase_k(base, k))[loff];
   };
   if (blockIdx.x < d.ntiles) load(blockIdx.x);
+  // The first tile's loads complete here, once: left in flight, they meet the
+  // loop's back edge at its header, and the compiler's wait there (sized for this
+  // entry) then also drains the previous tile's stores on every iteration, so
+  // that no store overlaps the next tile's work.
+  __builtin_amdgcn_s_waitcnt(0);
 
   double acc[MGK_NACC];
 #pragma unroll
