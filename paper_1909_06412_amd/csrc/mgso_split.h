@@ -159,7 +159,11 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
 #pragma unroll
   for (int k = 0; k < MGK_NACC; ++k) acc[k] = 0.0;
 
-  // LDS moves between the three line layouts (each followed by a barrier pair)
+  // LDS moves between the three line layouts.  A barrier follows each move into
+  // LDS and each read of the Y lines (the next tile's Z-line writes land on other
+  // threads' slots); none is needed between reading the X lines and writing them
+  // back, since a thread writes exactly the slots it read (the X-line slots of
+  // (thread, point) cover the tile once).
   // (pad16 of u + 16 m is pad16(u) + 17 m when u's low four bits stay below 16)
   constexpr uint32_t ZS = NT + NT / 16;
   auto z_to_lds = [&](C* x) {
@@ -200,7 +204,6 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
-      __syncthreads();
       dft16<T, true>(x);
       x_to_lds(x);
       __syncthreads();
@@ -231,7 +234,6 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
-      __syncthreads();
       dft16<T, false>(x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], mx[k]);
@@ -250,10 +252,13 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
         for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], m[j]);
         dft4(&x[4 * i], true);
       }
+      // pass C's A table is A_X A_Z, the same for every Y: one entry per Z line
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        const E ca = ltab[yg + 64u * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], ltab[yg + 16u * j + 64u * i], true);
+        for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], ca, true);
+      }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -266,7 +271,6 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       z_to_lds(x);
       __syncthreads();
       lds_to_x(x);
-      __syncthreads();
       dft16<T, false>(x);
       x_to_lds(x);
       __syncthreads();
