@@ -65,6 +65,18 @@ def test_create_rejects_bad_scalars(lib):
         assert st == _lib.MG_EINVAL
 
 
+@pytest.mark.parametrize("B,D", [(0, 2), (-1, 2), (1, 0), (1, 9)])
+def test_batch_create_rejects_bad_counts_without_touching_the_device(lib, B, D):
+    from paper_1909_06412_amd import _lib
+    h = ctypes.c_void_p()
+    N = np.full(max(B, 1) * max(D, 1), 64, dtype=np.int32)
+    dq = np.ones(max(B, 1) * max(D, 1))
+    st = lib.mg_batch_create(B, D, N.ctypes.data_as(_lib._ip), _lib.dptr(dq), _lib.dptr(dq), 1.0, 0,
+                             None, ctypes.byref(h))
+    assert st == _lib.MG_EINVAL
+    assert not h.value
+
+
 def test_null_context_calls_fail_cleanly(lib):
     from paper_1909_06412_amd import _lib
     assert lib.mg_step(None, 0.1, 1) == _lib.MG_EINVAL
