@@ -813,13 +813,43 @@ enum : int {
   EPI_SCALE = 16   // multiply by PacketState.scale
 };
 
+// Per-line factors of the two-dimensional atom-diatom potential (kind 2, D = 2:
+// a Morse well along axis 0 plus the repulsion A exp(-b (q_1 - c q_0))).  With
+// x_0 = q_0 - q_c,0 the repulsion factors into exp(b c x_0) exp(-b (q_1 - c q_c,0)),
+// so a grid needs 2 N_0 + N_1 exponentials instead of two per point:
+//   tab[j0] = exp(-a (q_0 - r_e)),  tab[N_0 + j0] = exp(b c x_0),
+//   tab[2 N_0 + j1] = exp(-b (q_1 - c q_c,0))
+// (the exponents stay within b c times half the span, whatever the centres).
+// Built by the whole workgroup; q_l as in epilogue_point.
+template <int NTHR>
+__device__ __forceinline__ void build_morse_tab(const PacketGeom& G, const PacketState& st, const PotDesc& P,
+                                                double* tab) {
+  const int n0 = G.ax[0].n, n1 = G.ax[1].n;
+  const double a = P.p[1], re = P.p[2], b = P.p[4], c = P.p[5];
+  for (int i = threadIdx.x; i < 2 * n0 + n1; i += NTHR) {
+    double v;
+    if (i < n0) {
+      const double q0 = st.q_c[0] + (double)(i - n0 / 2) * G.ax[0].dq;
+      v = exp(-a * (q0 - re));
+    } else if (i < 2 * n0) {
+      v = exp(b * c * ((double)(i - n0 - n0 / 2) * G.ax[0].dq));
+    } else {
+      const double q1 = st.q_c[1] + (double)(i - 2 * n0 - n1 / 2) * G.ax[1].dq;
+      v = exp(-b * (q1 - c * st.q_c[0]));
+    }
+    tab[i] = v;
+  }
+}
+
 // Pointwise work on one element with full multi-index j; returns the new value.
 // DT > 0 fixes the number of axes at compile time (specialised batch kernels).
+// mtab: the atom-diatom line factors of build_morse_tab (potential kind 2, D = 2),
+// or null to evaluate the potential point by point.
 template <typename T, int DT = 0>
 __device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::type x, const int* j,
                                                                const PacketGeom& G, const PacketState& st,
                                                                const PotDesc& P, int mode, double h,
-                                                               double* acc) {
+                                                               double* acc, const double* mtab = nullptr) {
   const int D = DT > 0 ? DT : G.D;
   if (mode & EPI_SCALE) {
     const T s = (T)st.scale;
@@ -857,9 +887,25 @@ __device__ __forceinline__ typename CT<T>::type epilogue_point(typename CT<T>::t
   }
   if (mode & EPI_V) {
     double q[MGK_MAXD], g[MGK_MAXD];
+    double V;
+    if (mtab) {
+      // the terms of pot_eval's kind 2 in its order, the exponentials from the table
+      const int n0 = G.ax[0].n;
+      const double e = mtab[j[0]];
+      const double rep = P.p[3] * (mtab[n0 + j[0]] * mtab[2 * n0 + j[1]]);
+      V = P.p[0] * (1.0 - e) * (1.0 - e);
+      double g0 = 2.0 * P.p[0] * P.p[1] * e * (1.0 - e);
+      V += rep;
+      g0 += P.p[4] * P.p[5] * rep;
+      g[0] = g0;
+      g[1] = -P.p[4] * rep;
 #pragma unroll
-    for (int l = 0; l < MGK_MAXD; ++l) q[l] = l < D ? st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq : 0.0;
-    const double V = pot_eval(P, D, q, g);
+      for (int l = 2; l < MGK_MAXD; ++l) g[l] = 0.0;
+    } else {
+#pragma unroll
+      for (int l = 0; l < MGK_MAXD; ++l) q[l] = l < D ? st.q_c[l] + (double)(j[l] - G.ax[l].n / 2) * G.ax[l].dq : 0.0;
+      V = pot_eval(P, D, q, g);
+    }
     acc[0] += w;
 #pragma unroll
     for (int l = 0; l < MGK_MAXD; ++l)

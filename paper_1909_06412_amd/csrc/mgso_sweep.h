@@ -87,7 +87,7 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
                                              const typename CT<T>::type* src, typename CT<T>::type* dst,
                                              const Tables<T>& tb, int dir, int epi, double h,
                                              const PacketState& st, const PotDesc& P, double* acc,
-                                             bool do_load, bool do_store) {
+                                             bool do_load, bool do_store, const double* mtab = nullptr) {
   typedef typename CT<T>::type C;
   const SweepDesc& sw = G.sw[si];
   const TileOrigin to = tile_origin(G, sw, tile);
@@ -151,7 +151,7 @@ __device__ __forceinline__ void process_tile(typename CT<T>::type* lds, const Pa
     if (epi) {
       int j[MGK_MAXD];
       decode_index(ad, D, sa, sb, o, g, i, j);
-      x = epilogue_point<T, DT>(x, j, G, st, P, epi, h, acc);
+      x = epilogue_point<T, DT>(x, j, G, st, P, epi, h, acc, mtab);
     }
     if (do_store) gstore(dst, gofs, x);
     else lds[t] = x;
