@@ -263,8 +263,67 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
           (dst + ybase(base, i, j))[loff] = x[4 * i + j];
         }
       }
+    } else if constexpr (KIND == SPL_C_MOM && sizeof(T) == 8) {
+      // momentum moments (complex128).  Each axis' moment needs only that axis transformed (the
+      // sum of |c|^2 over the other axes is the same in either representation), so
+      // the Z lines after their DFT give the total weight and the moments of Z, of
+      // the run (axis D-1) and of the tile constants; the X lines and the Y lines
+      // are both read from one LDS copy of that Z-transformed tile (one LDS write
+      // and two barriers per tile; complex128 13.9 -> 13.5 ms per launch, while the
+      // complex64 pass measured 8.1 -> 8.5 ms that way and keeps the layout of pass B
+      // below).  Axis axY has k = k0 + 4 k1 (k0 = oth, k1 = j).
+      constexpr int AX = SPL_AX[1][0], AZ = SPL_AX[1][1], AY = SPL_SPLIT_AXIS;
+      auto w2 = [](const C v) -> double { return (double)v.x * (double)v.x + (double)v.y * (double)v.y; };
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], ltab[zg + 64u * k]);
+      dft16<T, false>(x);
+      // The unnormalised DFTs scale the weights by 16 (dft16) and 4 (dft4): each sum
+      // is brought to that of the fully transformed tile (Z, X and Y done) by an exact
+      // power of two, 64 (Z lines), 4 (X lines) or 16 (Y lines), and goes into acc
+      // at once (fewer values live across the LDS moves).
+      {
+        double ws = 0.0, mz = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const double w = w2(x[k]);
+          ws += w;
+          mz += w * ((double)k - 8.0);
+        }
+        ws *= 64.0;
+        acc[0] += ws;
+        acc[1 + 7] += ws * ((double)(run | (base & 15u)) - 8.0);  // axis 7: the run and (complex128) bit 3
+        acc[1 + AZ] += 64.0 * mz;
+#pragma unroll
+        for (int l = 0; l < 7; ++l)
+          if (l != AX && l != AY && l != AZ)
+            acc[1 + l] += ws * ((double)((base >> (4 * (7 - l))) & 15u) - 8.0);
+      }
+      z_to_lds(x);
+      __syncthreads();
+      lds_to_x(x);
+      dft16<T, false>(x);
+      {
+        double mx = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) mx += w2(x[k]) * ((double)k - 8.0);
+        acc[1 + AX] += 4.0 * mx;
+      }
+      lds_to_y(x);
+      __syncthreads();
+      double wj[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dft4(&x[4 * i], false);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) wj[j] += w2(x[4 * i + j]);
+      }
+      double my = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) my += wj[j] * ((double)(oth + 4u * j) - 8.0);
+      acc[1 + AY] += 16.0 * my;
     } else {
-      // forward half: A factors, DFT along Z, X, then the 4-point Y digit
+      // forward half (pass B, and the complex64 moments): A factors, DFT along Z, X,
+      // then the 4-point Y digit
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], ltab[zg + 64u * k]);
       dft16<T, false>(x);
@@ -289,7 +348,7 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
           for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], s[j]);
       }
       if constexpr (KIND == SPL_C_MOM) {
-        // momentum moments: every axis is transformed; axis axY has k = k0 + 4 k1
+        // momentum moments of the fully transformed tile: axis axY has k = k0 + 4 k1
         // (k0 = oth, k1 = j), the run is axis D-1, the other axes are tile constants
         double wi[4] = {0.0, 0.0, 0.0, 0.0}, wj[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -317,7 +376,6 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
         for (int l = 0; l < 7; ++l)
           if (l != AX && l != AY && l != AZ)
             acc[1 + l] += ws * ((double)((base >> (4 * (7 - l))) & 15u) - 8.0);
-        continue;
       }
     }
     if constexpr (KIND == SPL_B_FWD) {
