@@ -123,6 +123,17 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
   const uint32_t yZb = 4u * wYs;
   const uint32_t yl = pad16(run + R * lX + 256u * R * wY);  // + 17 R j + 68 R i
   const uint32_t yg = lX + 256u * wY;                       // + 16 j + 64 i
+  // complex128 round trip: a thread's A factors (pass C's A_X A_Z at its fixed X; Z = k
+  // on load, Zb + i on store) are the same in every tile and stay in registers for the
+  // launch (complex64 has no registers to spare at 1024 threads)
+  constexpr bool AREG = KIND == SPL_C_RT && sizeof(T) == 8;
+  E areg[AREG ? 16 : 1], creg[AREG ? 4 : 1];
+  if constexpr (AREG) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) areg[k] = ltab[zg + 64u * k];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) creg[i] = ltab[yg + 64u * i];
+  }
 
   auto tile_base = [&](uint32_t tl) -> uint32_t {
     uint32_t b = 0, sh = 0;
@@ -226,7 +237,7 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
       const E* __restrict__ mx = lsm + 16;
       const E* __restrict__ mz = lsm + 32;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], ltab[zg + 64u * k]);
+      for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], AREG ? areg[AREG ? k : 0] : ltab[zg + 64u * k]);
       dft16<T, false>(x);
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = tmul<T>(x[k], mz[k]);
@@ -256,7 +267,7 @@ __global__ __launch_bounds__(spl_nt<T>()) void k_split(SplArgs<T> a) {
         for (int j = 0; j < 4; ++j) x[4 * i + j] = tmul<T>(x[4 * i + j], m[j]);
         dft4(&x[4 * i], true);
         // pass C's A table is A_X A_Z, the same for every Y: one entry per Z line
-        const E ca = ltab[yg + 64u * i];
+        const E ca = AREG ? creg[AREG ? i : 0] : ltab[yg + 64u * i];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           x[4 * i + j] = tmul<T>(x[4 * i + j], ca, true);
